@@ -1,0 +1,356 @@
+"""CPU oracle for the Fast-SegSim surfel feature rasterizer (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The GPU library never imports, links
+or executes anything in this package, and this package shares no code with it.
+
+The arithmetic lives in ``fso.c`` (plain C, double precision, built with
+``-ffp-contract=off``); this module is argument marshalling through ctypes
+plus the finite-difference driver used to pin the analytic gradient.
+
+Functions and the paper passage each follows:
+  project        tangent frame, T, adj(T), cutoff, culling    Sec. 3.1 Eq. (1), Sec. 3.2 (T)
+  tile_sets      per-pixel footprint test -> tiles            Sec. 3.2 (exact result of the
+                                                               precise tile intersection)
+  sort_pairs     (tile, depth) ordering                        Sec. 3.1 (depth-sorted surfels)
+  render_image / render_pixels
+                 front-to-back blend, full or Top-K            Sec. 3.1 Eq. (2), Sec. 3.4 F_TopK
+  render_grad    chain rule of the blend (held decisions)     training through the renderer, Sec. 3.5
+  finite_difference  central differences of render_image      (pins render_grad)
+
+Parity status: every function is pinned by tests under ``tests/`` (closed
+forms, brute force, invariants, finite differences).  The two readings the
+paper leaves open -- the exact projective conic in place of the garbled
+linearised covariance of Sec. 3.2, and "first K accepted contributors in depth
+order" for the Top-K set of Sec. 3.4 -- are pinned by those invariants only;
+the paper prints no worked values to pin them against.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfso.so")
+
+ALPHA_MIN = 1.0 / 255.0
+ALPHA_MAX = 0.99
+T_STOP = 1e-4
+
+_lib = None
+
+_d = ctypes.POINTER(ctypes.c_double)
+_i32 = ctypes.POINTER(ctypes.c_int32)
+_u32 = ctypes.POINTER(ctypes.c_uint32)
+_u64 = ctypes.POINTER(ctypes.c_uint64)
+_i64 = ctypes.POINTER(ctypes.c_int64)
+_i8 = ctypes.POINTER(ctypes.c_int8)
+
+
+def _ptr(a: np.ndarray, t):
+    return a.ctypes.data_as(t)
+
+
+def load():
+    """Load (building first if needed) the oracle shared library."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        from . import build as _build
+        _build.build()
+    lib = ctypes.CDLL(LIB_PATH)
+    I64, I32, D = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    lib.fso_project.argtypes = [_d, _d, _d, _d, I64, _d, D, _i32, _u32, _d, _d, _d]
+    lib.fso_surfel_d2_image.argtypes = [_d, I32, I32, _d]
+    lib.fso_conic_bounds.argtypes = [_d, D, _d]
+    lib.fso_conic_bounds.restype = I32
+    lib.fso_tile_sets.argtypes = [_i32, _u32, _d, _d, I64, I32, I32, I32, I32, I64, I64, _u32, _i8, _u64, _u32]
+    lib.fso_tile_sets.restype = I64
+    lib.fso_sort_pairs.argtypes = [_u64, _u32, I64]
+    lib.fso_tile_ranges.argtypes = [_u64, I64, I64, _u32]
+    lib.fso_render_pixels.argtypes = [_i32, _u32, _d, _d, _d, _d, I64, I32, I32, _i64, I64, D, D, D, I32, I32,
+                                      _d, _d, _d, _i32, _i32, _i32, _i32]
+    lib.fso_render_image.argtypes = [_i32, _u32, _d, _d, _d, _d, I64, I32, I32, I32, I32, D, D, D, I32, I32,
+                                     _d, _d, _d, _i32, _i32, _i32, _i32]
+    lib.fso_render_grad.argtypes = [_d, _d, _d, _d, _d, I64, I32, _d, I32, D, D, D, I32, _d, _d, _d, _d, _d, _d]
+    _lib = lib
+    return lib
+
+
+def camera_array(cam) -> np.ndarray:
+    """Pack a camera (width, height, fx, fy, cx, cy, R, t, z_near) as 19 doubles."""
+    return np.concatenate([[cam.width, cam.height, cam.fx, cam.fy, cam.cx, cam.cy],
+                           np.asarray(cam.R, np.float64).reshape(9), np.asarray(cam.t, np.float64).reshape(3),
+                           [cam.z_near]]).astype(np.float64)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+@dataclass
+class Projection:
+    valid: np.ndarray   # (N,) int32
+    zkey: np.ndarray    # (N,) uint32, float32 bits of the centre depth
+    T: np.ndarray       # (N, 3, 3) rows T1, T2, Tw
+    H: np.ndarray       # (N, 3, 3) adj(T): h = H (x, y, 1)
+    k2: np.ndarray      # (N,) cutoff 2 ln(o / alpha_min)
+
+
+def project(means, scales, quats, opacity, cam, alpha_min: float = ALPHA_MIN) -> Projection:
+    lib = load()
+    means, scales, quats, opacity = _f64(means), _f64(scales), _f64(quats), _f64(opacity)
+    n = means.shape[0]
+    valid = np.zeros(n, np.int32)
+    zkey = np.zeros(n, np.uint32)
+    T = np.zeros((n, 3, 3))
+    H = np.zeros((n, 3, 3))
+    k2 = np.zeros(n)
+    ca = camera_array(cam)
+    lib.fso_project(_ptr(means, _d), _ptr(scales, _d), _ptr(quats, _d), _ptr(opacity, _d), n, _ptr(ca, _d),
+                    float(alpha_min), _ptr(valid, _i32), _ptr(zkey, _u32), _ptr(T, _d), _ptr(H, _d), _ptr(k2, _d))
+    return Projection(valid, zkey, T, H, k2)
+
+
+def project_scene(scene, cam, alpha_min: float = ALPHA_MIN) -> Projection:
+    return project(scene.means, scene.scales, scene.quats, scene.opacity, cam, alpha_min)
+
+
+def surfel_d2_image(H: np.ndarray, width: int, height: int) -> np.ndarray:
+    """u^2 + v^2 at every pixel centre for one projected surfel, (height, width)."""
+    lib = load()
+    H = _f64(H).reshape(9)
+    out = np.zeros((height, width))
+    lib.fso_surfel_d2_image(_ptr(H, _d), width, height, _ptr(out, _d))
+    return out
+
+
+def conic_bounds(H: np.ndarray, k2: float):
+    lib = load()
+    H = _f64(H).reshape(9)
+    bb = np.zeros(4)
+    ok = lib.fso_conic_bounds(_ptr(H, _d), float(k2), _ptr(bb, _d))
+    return bb if ok else None
+
+
+def tile_sets(proj: Projection, width: int, height: int, tile: int, *, prefilter: bool = True,
+              tile_offset: int = 0, val_offset: int = 0, pairs: bool = False):
+    """Per-surfel tile counts (and optionally the unsorted pair list).
+
+    Returns (counts uint32 (N,), flags int8 (N,), keys uint64 (P,), vals uint32 (P,)).
+    """
+    lib = load()
+    n = proj.valid.shape[0]
+    counts = np.zeros(n, np.uint32)
+    flags = np.zeros(n, np.int8)
+    H = _f64(proj.H)
+    total = lib.fso_tile_sets(_ptr(proj.valid, _i32), _ptr(proj.zkey, _u32), _ptr(H, _d), _ptr(proj.k2, _d), n,
+                              width, height, tile, int(prefilter), tile_offset, val_offset, _ptr(counts, _u32),
+                              _ptr(flags, _i8), None, None)
+    if total < 0:
+        raise MemoryError("oracle tile_sets failed")
+    keys = vals = None
+    if pairs:
+        keys = np.zeros(max(total, 1), np.uint64)
+        vals = np.zeros(max(total, 1), np.uint32)
+        lib.fso_tile_sets(_ptr(proj.valid, _i32), _ptr(proj.zkey, _u32), _ptr(H, _d), _ptr(proj.k2, _d), n,
+                          width, height, tile, int(prefilter), tile_offset, val_offset, _ptr(counts, _u32),
+                          _ptr(flags, _i8), _ptr(keys, _u64), _ptr(vals, _u32))
+        keys, vals = keys[:total], vals[:total]
+    return counts, flags, keys, vals
+
+
+def sort_pairs(keys: np.ndarray, vals: np.ndarray):
+    lib = load()
+    keys = np.ascontiguousarray(keys, np.uint64).copy()
+    vals = np.ascontiguousarray(vals, np.uint32).copy()
+    lib.fso_sort_pairs(_ptr(keys, _u64), _ptr(vals, _u32), keys.shape[0])
+    return keys, vals
+
+
+def tile_ranges(keys: np.ndarray, num_tiles: int) -> np.ndarray:
+    lib = load()
+    keys = np.ascontiguousarray(keys, np.uint64)
+    ranges = np.zeros((num_tiles, 2), np.uint32)
+    if lib.fso_tile_ranges(_ptr(keys, _u64), keys.shape[0], num_tiles, _ptr(ranges, _u32)) != 0:
+        raise ValueError("tile id out of range")
+    return ranges
+
+
+def sorted_pairs(scene, cams, tile: int, alpha_min: float = ALPHA_MIN, prefilter: bool = True):
+    """Sorted (key, value) list over one or more views, tile ids offset per view
+    in view order and values = view * N + surfel index."""
+    cams = cams if isinstance(cams, (list, tuple)) else [cams]
+    ks, vs, tile_off = [], [], 0
+    n = scene.means.shape[0]
+    for v, cam in enumerate(cams):
+        proj = project_scene(scene, cam, alpha_min)
+        _, _, k, val = tile_sets(proj, cam.width, cam.height, tile, prefilter=prefilter, tile_offset=tile_off,
+                                 val_offset=v * n, pairs=True)
+        ks.append(k)
+        vs.append(val)
+        tile_off += ((cam.width + tile - 1) // tile) * ((cam.height + tile - 1) // tile)
+    keys, vals = sort_pairs(np.concatenate(ks), np.concatenate(vs))
+    return keys, vals, tile_off
+
+
+@dataclass
+class Render:
+    F: np.ndarray        # (..., C) blended features
+    absF: np.ndarray     # (..., C) sum of w |c|: error scale of F
+    T: np.ndarray        # (...)   final transmittance
+    n: np.ndarray        # (...)   number of blended surfels
+    idx: np.ndarray      # (..., kcap) blended surfel indices front to back, -1 padded
+    amb: np.ndarray      # (...)   1 if a threshold decision lies within 1e-5 relative
+    nclamp: np.ndarray   # (...)   how many contributors hit alpha_max
+
+
+def _render_common(proj, feats, opacity):
+    return _f64(feats), _f64(opacity), _f64(proj.H)
+
+
+def render_image(proj: Projection, opacity, feats, width: int, height: int, *, K: int = 0, kcap: int | None = None,
+                 alpha_min: float = ALPHA_MIN, alpha_max: float = ALPHA_MAX, t_stop: float = T_STOP,
+                 prefilter: bool = True) -> Render:
+    lib = load()
+    feats, opacity, H = _render_common(proj, feats, opacity)
+    n, C = feats.shape
+    kcap = int(kcap if kcap is not None else (K if K > 0 else 64))
+    npix = width * height
+    F = np.zeros((npix, C))
+    absF = np.zeros((npix, C))
+    T = np.zeros(npix)
+    nout = np.zeros(npix, np.int32)
+    idx = np.zeros((npix, max(kcap, 1)), np.int32)
+    amb = np.zeros(npix, np.int32)
+    ncl = np.zeros(npix, np.int32)
+    rc = lib.fso_render_image(_ptr(proj.valid, _i32), _ptr(proj.zkey, _u32), _ptr(H, _d), _ptr(proj.k2, _d),
+                              _ptr(opacity, _d), _ptr(feats, _d), n, C, width, height, int(prefilter), alpha_min,
+                              alpha_max, t_stop, K, kcap, _ptr(F, _d), _ptr(absF, _d), _ptr(T, _d),
+                              _ptr(nout, _i32), _ptr(idx, _i32), _ptr(amb, _i32), _ptr(ncl, _i32))
+    if rc != 0:
+        raise MemoryError("oracle render_image failed")
+    sh = (height, width)
+    return Render(F.reshape(sh + (C,)), absF.reshape(sh + (C,)), T.reshape(sh), nout.reshape(sh),
+                  idx.reshape(sh + (max(kcap, 1),))[..., :kcap], amb.reshape(sh), ncl.reshape(sh))
+
+
+def render_pixels(proj: Projection, opacity, feats, width: int, pix, *, K: int = 0, kcap: int | None = None,
+                  alpha_min: float = ALPHA_MIN, alpha_max: float = ALPHA_MAX, t_stop: float = T_STOP) -> Render:
+    """Brute-force render of selected pixels (pix = py * width + px)."""
+    lib = load()
+    feats, opacity, H = _render_common(proj, feats, opacity)
+    n, C = feats.shape
+    pix = np.ascontiguousarray(pix, np.int64)
+    m = pix.shape[0]
+    kcap = int(kcap if kcap is not None else (K if K > 0 else 64))
+    F = np.zeros((m, C))
+    absF = np.zeros((m, C))
+    T = np.zeros(m)
+    nout = np.zeros(m, np.int32)
+    idx = np.zeros((m, max(kcap, 1)), np.int32)
+    amb = np.zeros(m, np.int32)
+    ncl = np.zeros(m, np.int32)
+    lib.fso_render_pixels(_ptr(proj.valid, _i32), _ptr(proj.zkey, _u32), _ptr(H, _d), _ptr(proj.k2, _d),
+                          _ptr(opacity, _d), _ptr(feats, _d), n, C, width, _ptr(pix, _i64), m, alpha_min, alpha_max,
+                          t_stop, K, kcap, _ptr(F, _d), _ptr(absF, _d), _ptr(T, _d), _ptr(nout, _i32),
+                          _ptr(idx, _i32), _ptr(amb, _i32), _ptr(ncl, _i32))
+    return Render(F, absF, T, nout, idx[:, :kcap], amb, ncl)
+
+
+def render_scene(scene, cam, *, K: int = 0, kcap: int | None = None, alpha_min: float = ALPHA_MIN,
+                 alpha_max: float = ALPHA_MAX, t_stop: float = T_STOP, prefilter: bool = True,
+                 feats=None) -> Render:
+    proj = project_scene(scene, cam, alpha_min)
+    return render_image(proj, scene.opacity, scene.feats if feats is None else feats, cam.width, cam.height, K=K,
+                        kcap=kcap, alpha_min=alpha_min, alpha_max=alpha_max, t_stop=t_stop, prefilter=prefilter)
+
+
+@dataclass
+class Grads:
+    means: np.ndarray
+    scales: np.ndarray
+    quats: np.ndarray
+    opacity: np.ndarray
+    feats: np.ndarray
+
+
+def render_grad(means, scales, quats, opacity, feats, cam, g, *, K: int = 0, alpha_min: float = ALPHA_MIN,
+                alpha_max: float = ALPHA_MAX, t_stop: float = T_STOP, prefilter: bool = True) -> Grads:
+    """Gradient of sum(g * F) w.r.t. means, (activated) scales, raw quaternions,
+    (activated) opacity and features; g has shape (H, W, C)."""
+    lib = load()
+    means, scales, quats, opacity, feats = _f64(means), _f64(scales), _f64(quats), _f64(opacity), _f64(feats)
+    n, C = feats.shape
+    g = _f64(g).reshape(cam.height * cam.width, C)
+    gm, gs, gq = np.zeros((n, 3)), np.zeros((n, 2)), np.zeros((n, 4))
+    go, gf = np.zeros(n), np.zeros((n, C))
+    ca = camera_array(cam)
+    rc = lib.fso_render_grad(_ptr(means, _d), _ptr(scales, _d), _ptr(quats, _d), _ptr(opacity, _d), _ptr(feats, _d),
+                             n, C, _ptr(ca, _d), int(prefilter), alpha_min, alpha_max, t_stop, K, _ptr(g, _d),
+                             _ptr(gm, _d), _ptr(gs, _d), _ptr(gq, _d), _ptr(go, _d), _ptr(gf, _d))
+    if rc != 0:
+        raise MemoryError("oracle render_grad failed")
+    return Grads(gm, gs, gq, go, gf)
+
+
+# ---------------------------------------------------------------------------
+# Finite differences on the pre-activation parameters
+# ---------------------------------------------------------------------------
+
+def _forward_loss(params, cam, g, K, alpha_min, alpha_max, t_stop, kcap):
+    means, log_s, quats, logit_o, feats = params
+    scales = np.exp(log_s)
+    opacity = 1.0 / (1.0 + np.exp(-logit_o))
+    proj = project(means, scales, quats, opacity, cam, alpha_min)
+    r = render_image(proj, opacity, feats, cam.width, cam.height, K=K, kcap=kcap, alpha_min=alpha_min,
+                     alpha_max=alpha_max, t_stop=t_stop)
+    loss = float(np.sum(g * r.F))
+    # signature of the discrete decisions a derivative cannot see: the depth
+    # order of the surfels, which contributors hit the alpha clamp and, with
+    # Top-K, the selected sets.  Surfels entering or leaving a footprint at
+    # alpha = alpha_min change the loss by O(alpha_min) only.
+    order = np.lexsort((np.arange(proj.zkey.shape[0]), proj.zkey))
+    order = order[proj.valid[order] == 1]
+    sig = [order, r.nclamp.copy()]
+    if K > 0:
+        sig += [r.n.copy(), r.idx.copy()]
+    return loss, sig
+
+
+def _same_sig(a, b) -> bool:
+    return all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+def finite_difference(means, log_scales, quats, logit_opacity, feats, cam, g, coords, *, h: float = 1e-3,
+                      K: int = 0, alpha_min: float = 1e-12, alpha_max: float = ALPHA_MAX, t_stop: float = 0.0,
+                      kcap: int = 512):
+    """Central differences of L = sum(g * F) for the listed scalar coordinates.
+
+    coords: iterable of (group, index tuple) with group in
+    {"means", "log_scales", "quats", "logit_opacity", "feats"}.  Returns a list
+    of (value or None); None marks a coordinate whose discrete decisions
+    (contributor lists, clamp states) differ between theta - h, theta and
+    theta + h, where a central difference is not a derivative.
+    """
+    names = ["means", "log_scales", "quats", "logit_opacity", "feats"]
+    base = [_f64(means).copy(), _f64(log_scales).copy(), _f64(quats).copy(), _f64(logit_opacity).copy(),
+            _f64(feats).copy()]
+    _, sig0 = _forward_loss(base, cam, g, K, alpha_min, alpha_max, t_stop, kcap)
+    out = []
+    for group, index in coords:
+        gi = names.index(group)
+        vals = []
+        ok = True
+        for sgn in (+1.0, -1.0):
+            p = [a.copy() for a in base]
+            p[gi][index] += sgn * h
+            loss, sig = _forward_loss(p, cam, g, K, alpha_min, alpha_max, t_stop, kcap)
+            ok = ok and _same_sig(sig, sig0)
+            vals.append(loss)
+        out.append((vals[0] - vals[1]) / (2 * h) if ok else None)
+    return out

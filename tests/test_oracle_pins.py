@@ -1,0 +1,368 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+No test here re-types an oracle formula: the references are closed forms, an
+independent ray-plane intersection with scipy's rotation, pure-Python brute
+force on tiny inputs, numpy sorting, invariants of the blend (Eq. 2 and the
+Top-K restriction of Sec. 3.4), and central finite differences.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_10951_amd import scenes
+from tests import _indep
+
+A_MIN, A_MAX, T_STOP = 1 / 255, 0.99, 1e-4
+
+
+def _tilted_scene(n, seed, cam_rot=True):
+    """Tiny scene of random tilted surfels in front of a rotated, off-centre camera."""
+    rng = np.random.default_rng(seed)
+    W, H = 24, 20
+    if cam_rot:
+        R = _indep.rotation(rng.standard_normal(4) * np.array([3, 0.2, 0.2, 0.2]) + np.array([1, 0, 0, 0]))
+    else:
+        R = np.eye(3)
+    cam = scenes.Camera(W, H, 22.0, 19.0, 11.3, 9.1, R.astype(np.float32), np.array([0.1, -0.2, 0.3], np.float32))
+    # place centres in camera space, then map to world
+    pc = np.stack([rng.uniform(-0.4, 0.4, n), rng.uniform(-0.4, 0.4, n), rng.uniform(2.0, 4.0, n)], 1)
+    Rd = cam.R.astype(np.float64)
+    means = ((pc - cam.t.astype(np.float64)) @ Rd).astype(np.float32)   # R^T (pc - t)
+    scales = np.exp(rng.uniform(np.log(0.05), np.log(0.3), (n, 2))).astype(np.float32)
+    q = rng.standard_normal((n, 4))
+    q[:, 0] = np.abs(q[:, 0]) + 1.0         # keep surfels from being edge-on too often
+    quats = (q / np.linalg.norm(q, axis=1, keepdims=True)).astype(np.float32)
+    opacity = rng.uniform(0.2, 0.95, n).astype(np.float32)
+    feats = rng.standard_normal((n, 5)).astype(np.float32)
+    return scenes.Scene(means, scales, quats, opacity, feats), cam
+
+
+# ---------------------------------------------------------------------------
+# Projection and the ray-splat intersection (Sec. 3.1 / 3.2)
+# ---------------------------------------------------------------------------
+
+def test_fronto_parallel_splat_is_textbook_gaussian():
+    """A surfel facing the camera renders u^2+v^2 = ((x-x0)/sx)^2 + ((y-y0)/sy)^2
+    with sx = r_u fx / Z and (x0, y0) the pinhole projection of its centre."""
+    cam = scenes.Camera(40, 30, 50.0, 45.0, 20.5, 14.25)
+    X, Y, Z = 0.13, -0.07, 3.0
+    su, sv = 0.21, 0.12
+    proj = oracle.project([[X, Y, Z]], [[su, sv]], [[1.0, 0.0, 0.0, 0.0]], [0.7], cam)
+    assert proj.valid[0] == 1
+    d2 = oracle.surfel_d2_image(proj.H[0], cam.width, cam.height)
+    x0, y0 = cam.fx * X / Z + cam.cx, cam.fy * Y / Z + cam.cy
+    sx, sy = su * cam.fx / Z, sv * cam.fy / Z
+    xs = np.arange(cam.width) + 0.5
+    ys = np.arange(cam.height) + 0.5
+    ref = ((xs[None, :] - x0) / sx) ** 2 + ((ys[:, None] - y0) / sy) ** 2
+    np.testing.assert_allclose(d2, ref, rtol=1e-12, atol=1e-12)
+    # and the cutoff is the opacity-aware one: alpha >= 1/255 <=> d2 <= 2 ln(255 o)
+    assert proj.k2[0] == pytest.approx(2 * np.log(0.7 * 255), rel=1e-15)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_tilted_splat_matches_world_space_ray_plane(seed):
+    sc, cam = _tilted_scene(12, seed)
+    proj = oracle.project_scene(sc, cam)
+    rng = np.random.default_rng(100 + seed)
+    checked = 0
+    for i in range(sc.n):
+        if not proj.valid[i]:
+            continue
+        d2 = oracle.surfel_d2_image(proj.H[i], cam.width, cam.height)
+        near = np.argwhere(d2 < 60)
+        picks = [tuple(near[j][::-1]) for j in rng.permutation(len(near))[:6]]
+        picks += [(int(rng.integers(0, cam.width)), int(rng.integers(0, cam.height))) for _ in range(3)]
+        for px, py in picks:
+            u, v, lam = _indep.ray_plane_uv(sc.means[i], sc.scales[i].astype(np.float64), sc.quats[i], cam,
+                                            px + 0.5, py + 0.5)
+            ref = u * u + v * v
+            if lam <= 0:
+                # the ray meets the plane behind the camera: the disk is culled
+                # to lie in front, so such pixels must be outside the footprint
+                assert d2[py, px] > proj.k2[i]
+                continue
+            # far outside the footprint the ray grazes the plane and both
+            # solutions lose digits; inside a few cutoffs they agree to 1e-10
+            assert d2[py, px] == pytest.approx(ref, rel=1e-10 if ref < 60 else 1e-6, abs=1e-12)
+            checked += ref < 60
+    assert checked >= 30
+
+
+def test_T_maps_tangent_origin_to_pinhole_projection():
+    """T (0, 0, 1)^T = K_int p_c, the textbook projection of the centre (Sec. 3.2)."""
+    sc, cam = _tilted_scene(10, 5)
+    proj = oracle.project_scene(sc, cam)
+    K = np.array([[cam.fx, 0, cam.cx], [0, cam.fy, cam.cy], [0, 0, 1.0]])
+    for i in np.nonzero(proj.valid)[0]:
+        pc = cam.R.astype(np.float64) @ sc.means[i].astype(np.float64) + cam.t
+        np.testing.assert_allclose(proj.T[i] @ np.array([0, 0, 1.0]), K @ pc, rtol=1e-12)
+        # and T (u, v, 1) is the projection of the tangent point p + u r_u t_u + v r_v t_v (Eq. 1)
+        Rq = _indep.rotation(sc.quats[i])
+        u, v = 0.3, -0.7
+        pw = sc.means[i] + u * sc.scales[i, 0] * Rq[:, 0] + v * sc.scales[i, 1] * Rq[:, 1]
+        xh = K @ (cam.R.astype(np.float64) @ pw + cam.t)
+        np.testing.assert_allclose(proj.T[i] @ np.array([u, v, 1.0]), xh, rtol=1e-7)
+
+
+def test_depth_key_is_float32_bits_of_camera_depth():
+    sc, cam = _tilted_scene(40, 7)
+    proj = oracle.project_scene(sc, cam)
+    for i in range(sc.n):
+        z = np.float32(_indep.camera_depth(sc.means[i], cam))
+        assert proj.zkey[i] == z.view(np.uint32)
+    # keys of positive depths order like the depths
+    order_k = np.argsort(proj.zkey, kind="stable")
+    z = np.array([_indep.camera_depth(m, cam) for m in sc.means])
+    assert np.all(np.diff(z[order_k]) >= -1e-6)
+
+
+def test_culling_rules():
+    cam = scenes.centred_camera(32, 32)
+    base = dict(means=[0.0, 0.0, 3.0], scales=[0.05, 0.05], quats=[1.0, 0, 0, 0], opacity=0.6)
+    cases = {
+        "ok": {},
+        "behind": dict(means=[0.0, 0.0, -3.0]),
+        "near": dict(means=[0.0, 0.0, 0.1]),
+        "low_opacity": dict(opacity=1 / 255),
+        "zero_quat": dict(quats=[0.0, 0, 0, 0]),
+        "nan": dict(means=[np.nan, 0.0, 3.0]),
+        "zero_scale": dict(scales=[0.0, 0.05]),
+        "edge_on": dict(quats=[np.cos(np.pi / 4), np.sin(np.pi / 4), 0, 0], means=[0.0, 0.0, 3.0]),
+        "disk_crosses_near": dict(means=[0.0, 0.0, 0.5], scales=[0.5, 0.5],
+                                  quats=[np.cos(np.pi / 8), np.sin(np.pi / 8), 0, 0]),
+    }
+    for name, over in cases.items():
+        p = dict(base, **over)
+        proj = oracle.project([p["means"]], [p["scales"]], [p["quats"]], [p["opacity"]], cam)
+        assert proj.valid[0] == (1 if name == "ok" else 0), name
+
+
+def test_unnormalised_quaternion_gives_same_frame():
+    sc, cam = _tilted_scene(8, 3)
+    q2 = sc.quats * np.float32(3.0)
+    a = oracle.project(sc.means, sc.scales, sc.quats, sc.opacity, cam)
+    b = oracle.project(sc.means, sc.scales, q2, sc.opacity, cam)
+    np.testing.assert_allclose(a.H, b.H, rtol=1e-6, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Tile sets (Sec. 3.2): the per-pixel definition by brute force
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tile", [4, 8])
+def test_tile_sets_equal_brute_force(tile):
+    sc, cam = _tilted_scene(25, 11)
+    proj = oracle.project_scene(sc, cam)
+    counts, flags, keys, vals = oracle.tile_sets(proj, cam.width, cam.height, tile, prefilter=False, pairs=True)
+    assert not flags.any()
+    tx_n = (cam.width + tile - 1) // tile
+    got = {}
+    for k, v in zip(keys, vals):
+        got.setdefault(int(v), set()).add(int(k >> np.uint64(32)))
+    for i in range(sc.n):
+        ref = set()
+        if proj.valid[i]:
+            for py in range(cam.height):
+                for px in range(cam.width):
+                    u, v, lam = _indep.ray_plane_uv(sc.means[i], sc.scales[i].astype(np.float64), sc.quats[i],
+                                                    cam, px + 0.5, py + 0.5)
+                    if u * u + v * v <= proj.k2[i]:
+                        ref.add((py // tile) * tx_n + px // tile)
+        assert got.get(i, set()) == ref, i
+        assert counts[i] == len(ref)
+
+
+def test_tile_set_prefilter_is_conservative():
+    sc, cam = scenes.parity_small()
+    sc = sc.subset(np.arange(600))
+    proj = oracle.project_scene(sc, cam)
+    c0, f0, k0, v0 = oracle.tile_sets(proj, cam.width, cam.height, 16, prefilter=False, pairs=True)
+    c1, f1, k1, v1 = oracle.tile_sets(proj, cam.width, cam.height, 16, prefilter=True, pairs=True)
+    np.testing.assert_array_equal(c0, c1)
+    np.testing.assert_array_equal(k0, k1)
+    np.testing.assert_array_equal(v0, v1)
+
+
+def test_conic_bounds_fronto_parallel_closed_form():
+    cam = scenes.Camera(64, 64, 80.0, 80.0, 32.0, 32.0)
+    proj = oracle.project([[0.2, -0.1, 4.0]], [[0.3, 0.15]], [[1.0, 0, 0, 0]], [0.5], cam)
+    bb = oracle.conic_bounds(proj.H[0], proj.k2[0])
+    k = np.sqrt(proj.k2[0])
+    x0, y0 = 80 * 0.2 / 4 + 32, 80 * -0.1 / 4 + 32
+    sx, sy = 0.3 * 80 / 4, 0.15 * 80 / 4
+    np.testing.assert_allclose(bb, [x0 - k * sx, x0 + k * sx, y0 - k * sy, y0 + k * sy], rtol=1e-12)
+
+
+def test_sort_and_ranges_match_numpy():
+    sc, cam = scenes.parity_small()
+    keys, vals, ntiles = oracle.sorted_pairs(sc, cam, 16)
+    proj = oracle.project_scene(sc, cam)
+    _, _, k_raw, v_raw = oracle.tile_sets(proj, cam.width, cam.height, 16, pairs=True)
+    order = np.lexsort((v_raw, k_raw))
+    np.testing.assert_array_equal(keys, k_raw[order])
+    np.testing.assert_array_equal(vals, v_raw[order])
+    ranges = oracle.tile_ranges(keys, ntiles)
+    tiles = (keys >> np.uint64(32)).astype(np.int64)
+    for t in range(ntiles):
+        s, e = np.searchsorted(tiles, t, "left"), np.searchsorted(tiles, t, "right")
+        if e > s:
+            assert tuple(ranges[t]) == (s, e)
+        else:
+            assert ranges[t, 1] - ranges[t, 0] == 0
+
+
+# ---------------------------------------------------------------------------
+# Blending (Eq. 2) and Top-K (Sec. 3.4)
+# ---------------------------------------------------------------------------
+
+def test_one_and_two_splats_by_hand():
+    """F = alpha1 c1 + alpha2 (1 - alpha1) c2 for two fronto-parallel splats,
+    with alpha = o exp(-(u^2+v^2)/2) evaluated in closed form."""
+    cam = scenes.Camera(8, 8, 8.0, 8.0, 4.0, 4.0)
+    means = [[0.0, 0.0, 4.0], [0.0, 0.0, 2.0]]           # second one is in front
+    sc = scenes.Scene(np.array(means, np.float32), np.array([[0.5, 0.5], [0.25, 0.25]], np.float32),
+                      np.array([[1, 0, 0, 0], [1, 0, 0, 0]], np.float32), np.array([0.5, 0.8], np.float32),
+                      np.array([[0.0, 1.0, 1.0], [1.0, 0.0, 1.0]], np.float32))
+    r = oracle.render_scene(sc, cam)
+    # pixel (4, 4): centre (4.5, 4.5); both splats have sigma = 1 px there, u = v = 0.5
+    a_front = float(np.float32(0.8)) * np.exp(-0.25)    # opacities are stored as float32
+    a_back = 0.5 * np.exp(-0.25)
+    ref = a_front * np.array([1.0, 0.0, 1.0]) + a_back * (1 - a_front) * np.array([0.0, 1.0, 1.0])
+    np.testing.assert_allclose(r.F[4, 4], ref, rtol=1e-12)
+    assert r.n[4, 4] == 2
+    assert list(r.idx[4, 4, :2]) == [1, 0]
+    assert r.T[4, 4] == pytest.approx((1 - a_front) * (1 - a_back), rel=1e-12)
+    # one splat alone: F = alpha c
+    r1 = oracle.render_scene(sc.subset([0]), cam)
+    np.testing.assert_allclose(r1.F[4, 4], 0.5 * np.exp(-0.25) * np.array([0.0, 1.0, 1.0]), rtol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_blend_matches_pure_python_brute_force(seed):
+    sc, cam = _tilted_scene(30, 20 + seed)
+    proj = oracle.project_scene(sc, cam)
+    assert proj.valid.all()
+    r = oracle.render_image(proj, sc.opacity, sc.feats, cam.width, cam.height, kcap=64)
+    rk = oracle.render_image(proj, sc.opacity, sc.feats, cam.width, cam.height, K=3)
+    rng = np.random.default_rng(seed)
+    pix = [(int(rng.integers(0, cam.width)), int(rng.integers(0, cam.height))) for _ in range(40)]
+    ref = _indep.brute_blend(sc, cam, pix)
+    refk = _indep.brute_blend(sc, cam, pix, K=3)
+    for (px, py), (F, T, who), (Fk, Tk, whok) in zip(pix, ref, refk):
+        if r.amb[py, px]:
+            continue
+        np.testing.assert_allclose(r.F[py, px], F, rtol=1e-9, atol=1e-12)
+        assert r.T[py, px] == pytest.approx(T, rel=1e-9)
+        assert list(r.idx[py, px, :r.n[py, px]]) == who
+        np.testing.assert_allclose(rk.F[py, px], Fk, rtol=1e-9, atol=1e-12)
+        assert list(rk.idx[py, px, :rk.n[py, px]]) == whok
+
+
+def test_blend_invariants_on_parity_scene():
+    sc, cam = scenes.parity_small()
+    feats = np.concatenate([sc.feats, np.ones((sc.n, 1), np.float32)], 1)   # constant channel
+    proj = oracle.project_scene(sc, cam)
+    r = oracle.render_image(proj, sc.opacity, feats, cam.width, cam.height, kcap=256)
+    # sum of weights = 1 - T_final (telescoping product)
+    np.testing.assert_allclose(r.F[..., -1], 1 - r.T, rtol=0, atol=1e-12)
+    assert np.all(r.T >= T_STOP) and np.all(r.T <= 1)
+    assert np.all(r.F[..., -1] >= 0)
+    cmax = np.abs(feats).max(0)
+    assert np.all(np.abs(r.F) <= (1 - r.T)[..., None] * cmax + 1e-12)
+    assert r.n.max() > 5 and (r.n > 0).mean() > 0.3
+    # empty pixels are exactly zero with T = 1
+    empty = r.n == 0
+    assert np.all(r.F[empty] == 0) and np.all(r.T[empty] == 1)
+
+
+def test_topk_prefix_and_truncation_bound():
+    sc, cam = scenes.parity_small()
+    proj = oracle.project_scene(sc, cam)
+    full = oracle.render_image(proj, sc.opacity, sc.feats, cam.width, cam.height, kcap=256)
+    cmax = np.abs(sc.feats).max()
+    for K in (1, 2, 4, 8):
+        rk = oracle.render_image(proj, sc.opacity, sc.feats, cam.width, cam.height, K=K)
+        assert np.all(rk.n == np.minimum(full.n, K))
+        # the selected set is the first K contributors of the full blend
+        for py, px in zip(*np.nonzero(full.n > 0)):
+            m = rk.n[py, px]
+            assert np.array_equal(rk.idx[py, px, :m], full.idx[py, px, :m])
+        # |F_full - F_K| <= T after the K-th contributor * max |c|
+        assert np.all(np.abs(full.F - rk.F) <= rk.T[..., None] * cmax + 1e-12)
+        if K == 1:
+            sel = rk.n == 1
+            i = rk.idx[sel, 0]
+            np.testing.assert_allclose(rk.F[sel], (1 - rk.T[sel])[:, None] * sc.feats[i], rtol=1e-12, atol=1e-12)
+    # K >= longest list: identical to the full blend
+    big = oracle.render_image(proj, sc.opacity, sc.feats, cam.width, cam.height, K=int(full.n.max()) + 1, kcap=256)
+    np.testing.assert_array_equal(big.F, full.F)
+    np.testing.assert_array_equal(big.T, full.T)
+
+
+def test_render_routes_agree():
+    """Whole-image route (with and without the conic prefilter) equals the
+    per-pixel brute force over every surfel."""
+    sc, cam = scenes.parity_small()
+    sc = sc.subset(np.arange(400))
+    proj = oracle.project_scene(sc, cam)
+    a = oracle.render_image(proj, sc.opacity, sc.feats, cam.width, cam.height, K=4, prefilter=True)
+    b = oracle.render_image(proj, sc.opacity, sc.feats, cam.width, cam.height, K=4, prefilter=False)
+    pix = np.arange(cam.width * cam.height)[::7]
+    c = oracle.render_pixels(proj, sc.opacity, sc.feats, cam.width, pix, K=4)
+    for name in ("F", "T", "n", "idx", "amb"):
+        np.testing.assert_array_equal(getattr(a, name), getattr(b, name))
+        np.testing.assert_array_equal(getattr(a, name).reshape((cam.width * cam.height,) +
+                                                               getattr(a, name).shape[2:])[pix], getattr(c, name))
+
+
+def test_empty_scene_and_no_valid_surfels():
+    cam = scenes.centred_camera(16, 16)
+    sc = scenes.Scene(np.array([[0, 0, -5.0]], np.float32), np.array([[0.1, 0.1]], np.float32),
+                      np.array([[1, 0, 0, 0]], np.float32), np.array([0.9], np.float32), np.ones((1, 3), np.float32))
+    r = oracle.render_scene(sc, cam)
+    assert np.all(r.F == 0) and np.all(r.T == 1) and np.all(r.n == 0)
+
+
+# ---------------------------------------------------------------------------
+# Gradient (chain rule of the blend) against central differences
+# ---------------------------------------------------------------------------
+
+def _fd_scene():
+    sc, cam = _tilted_scene(10, 31, cam_rot=True)
+    sc.scales *= np.float32(0.35)   # keep the wide smooth-mode footprints inside the image
+    sc.feats = sc.feats[:, :3].copy()
+    return sc, cam
+
+
+@pytest.mark.parametrize("K", [0, 2])
+def test_gradient_matches_finite_differences(K):
+    sc, cam = _fd_scene()
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal((cam.height, cam.width, sc.channels))
+    amin, tstop = 1e-12, 0.0
+    log_s = np.log(sc.scales.astype(np.float64))
+    logit = np.log(sc.opacity.astype(np.float64) / (1 - sc.opacity.astype(np.float64)))
+    scales = np.exp(log_s)
+    opac = 1 / (1 + np.exp(-logit))
+    gr = oracle.render_grad(sc.means, scales, sc.quats, opac, sc.feats, cam, g, K=K, alpha_min=amin, t_stop=tstop)
+    analytic = {"means": gr.means, "log_scales": gr.scales * scales, "quats": gr.quats,
+                "logit_opacity": gr.opacity * opac * (1 - opac), "feats": gr.feats}
+    coords = []
+    for i in range(sc.n):
+        coords += [("means", (i, k)) for k in range(3)] + [("log_scales", (i, k)) for k in range(2)]
+        coords += [("quats", (i, k)) for k in range(4)] + [("logit_opacity", (i,))]
+        coords += [("feats", (i, k)) for k in range(sc.channels)]
+    fd = oracle.finite_difference(sc.means, log_s, sc.quats, logit, sc.feats, cam, g, coords, h=1e-6, K=K,
+                                  alpha_min=amin, t_stop=tstop)
+    valid = 0
+    for (grp, idx), f in zip(coords, fd):
+        if f is None:
+            continue
+        a = analytic[grp][idx]
+        scale = np.abs(analytic[grp]).max()
+        assert abs(a - f) <= 1e-4 * abs(a) + 1e-6 * scale + 1e-9, (grp, idx, a, f)
+        valid += 1
+    assert valid >= 0.6 * len(coords)
