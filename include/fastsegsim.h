@@ -1,0 +1,219 @@
+/*
+ * fastsegsim.h -- C ABI of the MI355X (gfx950) surfel feature rasterizer.
+ *
+ * The library renders C-channel feature images from 2D Gaussian surfels, the
+ * rendering path of Fast-SegSim (arXiv 2604.10951):
+ *
+ *   fs_preprocess       per (view, surfel): tangent frame, the homogeneous
+ *                       tangent->screen matrix T, depth key, culling, the
+ *                       screen conic and the count of tiles it touches
+ *                       (Sec. 3.1 Eq. 1; Sec. 3.2 "Perspective-Corrected
+ *                       Conic Matrix Derivation", "Snugbox and AccuTile")
+ *   fs_bin              exclusive scan of the tile counts and emission of one
+ *                       (tile, depth) key per touched tile (Sec. 3.2)
+ *   fs_sort             stable radix sort of the keys and per-tile ranges
+ *                       (surfels are blended depth-sorted, Sec. 3.1)
+ *   fs_render_forward   per-pixel front-to-back blending of C-channel features,
+ *                       full (Sec. 3.1 Eq. 2) or Top-K hard selection
+ *                       (Sec. 3.4, F_TopK)
+ *   fs_render_backward  gradients of a loss on the rendered features w.r.t.
+ *                       surfel centres, scales, rotations, opacities and
+ *                       features (the renderer is trained end to end, Sec. 3.5)
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named *_dev, and every array argument unless stated otherwise,
+ *     are DEVICE memory owned by the caller.  The library never allocates,
+ *     frees or keeps pointers beyond a call; scratch memory comes from the
+ *     caller's `workspace` (size from fs_workspace_bytes).
+ *   - Work is enqueued on `stream` in call order.  Calls return after
+ *     enqueueing; the only host synchronisation is fs_bin's optional readback
+ *     of the pair count (num_pairs_host != NULL).
+ *   - Arguments are validated before anything is enqueued: FS_ERR_ARG means
+ *     nothing ran.  A failed launch returns FS_ERR_HIP (the HIP error is
+ *     available through fs_last_hip_error).  No entry point aborts or throws.
+ *   - Calls that share a workspace must not overlap; distinct workspaces may
+ *     run concurrently on different streams.
+ *
+ * Scene arrays (float32, row-major, N surfels):
+ *   means   N x 3   world-space centre p (Sec. 3.1 Eq. 1)
+ *   scales  N x 2   tangent scales (r_u, r_v), linear, > 0
+ *   quats   N x 4   rotation (w, x, y, z), need not be unit length; columns 0
+ *                   and 1 of its rotation matrix are t_u and t_v
+ *   opacity N       o in (0, 1)
+ *   feats   N x C   per-surfel feature vector c (float32 or bfloat16)
+ *
+ * Per-view outputs are packed view after view; view v starts at pixel
+ * cams[v].pixel_offset (set by fs_layout_views).  Pixel (px, py) of view v is
+ * element pixel_offset + py * width + px, and its sample point is the pixel
+ * centre (px + 0.5, py + 0.5).
+ */
+#ifndef FASTSEGSIM_H
+#define FASTSEGSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fs_status {
+    FS_OK = 0,
+    FS_ERR_ARG = 1,         /* invalid argument; nothing was enqueued */
+    FS_ERR_CAPACITY = 2,    /* the key/value buffers are too small for the pair count */
+    FS_ERR_HIP = 3,         /* a HIP launch or runtime call failed */
+    FS_ERR_UNSUPPORTED = 4  /* a valid but unimplemented option combination */
+} fs_status;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward).  A world point p
+ * maps to camera space as p_c = R p + t; intrinsics K = [[fx,0,cx],[0,fy,cy],
+ * [0,0,1]] (the camera part of T in Sec. 3.2).  88 bytes. */
+typedef struct fs_camera {
+    int32_t width, height;  /* pixels */
+    float fx, fy, cx, cy;
+    float R[9];             /* world -> camera rotation, row-major */
+    float t[3];             /* world -> camera translation */
+    float z_near;           /* surfels whose cutoff disk reaches depth <= z_near are culled */
+    int32_t tile_offset;    /* first global tile id of this view (fs_layout_views) */
+    int64_t pixel_offset;   /* first packed pixel of this view (fs_layout_views) */
+} fs_camera;
+
+enum { FS_TILES_PRECISE = 0, FS_TILES_BBOX = 1 };
+enum { FS_FEAT_F32 = 0, FS_FEAT_BF16 = 1 };
+
+typedef struct fs_opts {
+    int32_t tile;        /* binning tile side in pixels: 8, 16 or 32 */
+    int32_t topk;        /* 0: full blend (Eq. 2); K in [1, 64]: Top-K hard selection (Sec. 3.4) */
+    int32_t tile_mode;   /* FS_TILES_PRECISE: exact footprint tiles (SnugBox + AccuTile);
+                            FS_TILES_BBOX: every tile of the ellipse's circumscribed square */
+    int32_t feat_dtype;  /* FS_FEAT_F32 or FS_FEAT_BF16 storage of feats (math is float32) */
+    float alpha_min;     /* a surfel contributes to a pixel iff o f(u) >= alpha_min (1/255) */
+    float alpha_max;     /* alpha = min(alpha_max, o f(u)) (0.99) */
+    float t_stop;        /* a pixel stops before the surfel that would take its
+                            transmittance below t_stop (1e-4) */
+    int32_t batch;       /* list entries staged in LDS per step: 16 or 32 (0 = 32) */
+} fs_opts;
+
+/* Size of the record fs_preprocess writes per (view, surfel). */
+#define FS_RECORD_BYTES 96
+/* Floats of per-record geometry gradient fs_render_backward accumulates. */
+#define FS_GRAD_RECORD_FLOATS 12
+
+/*
+ * fs_layout_views (host only): fill cams_host[v].tile_offset and
+ * .pixel_offset for views packed in order, for the given tile size, and
+ * return the totals.  cams_host is HOST memory.  FS_ERR_ARG on a bad tile
+ * size, a non-positive image size or an image wider than 32767 pixels.
+ */
+fs_status fs_layout_views(fs_camera* cams_host, int32_t num_views, int32_t tile, int64_t* total_tiles,
+                          int64_t* total_pixels);
+
+/*
+ * fs_workspace_bytes (host only): scratch bytes every stage needs for n
+ * surfels, num_views views, total_tiles tiles and pair_capacity key/value
+ * slots.  One workspace serves all stages of a frame.
+ */
+size_t fs_workspace_bytes(int64_t n, int32_t num_views, int64_t total_tiles, int64_t pair_capacity,
+                          const fs_opts* opts);
+
+/*
+ * fs_preprocess (Sec. 3.1 Eq. 1; Sec. 3.2).  For every view v and surfel i:
+ * tangent frame from the quaternion, camera-space frame, T = K [U | V | p_c],
+ * the depth key (float32 bits of the centre's camera depth), culling, the
+ * cutoff k^2 = 2 ln(o / alpha_min), the screen conic of u^2+v^2 = k^2 and its
+ * tile count (exact per-pixel footprint for FS_TILES_PRECISE).
+ *   records        out, num_views * n * FS_RECORD_BYTES, record v*n+i
+ *   tiles_touched  out, num_views * n uint32 (0 for culled surfels)
+ * cams_dev is a device array of num_views cameras laid out by fs_layout_views.
+ */
+fs_status fs_preprocess(const float* means, const float* scales, const float* quats, const float* opacity, int64_t n,
+                        const fs_camera* cams_dev, int32_t num_views, const fs_opts* opts, void* records,
+                        uint32_t* tiles_touched, hipStream_t stream);
+
+/*
+ * fs_bin (Sec. 3.2).  Exclusive scan of tiles_touched over (view, surfel) in
+ * record order, then every surfel re-derives its footprint from its
+ * parameters (bit-identical to fs_preprocess) and writes, for each touched
+ * tile, key = (global tile id << 32) | depth key and value = record index
+ * v*n+i at its scanned offset.
+ *   keys, vals       out, pair_capacity slots each
+ *   num_pairs_dev    out, device int64: the pair count P (written even if it
+ *                    exceeds pair_capacity; then keys beyond capacity are dropped)
+ *   num_pairs_host   optional HOST int64: if non-NULL the call waits for P,
+ *                    stores it and returns FS_ERR_CAPACITY when P > pair_capacity.
+ */
+fs_status fs_bin(const float* means, const float* scales, const float* quats, const float* opacity, int64_t n,
+                 const fs_camera* cams_dev, int32_t num_views, const fs_opts* opts, const uint32_t* tiles_touched,
+                 uint64_t* keys, uint32_t* vals, int64_t pair_capacity, int64_t* num_pairs_dev,
+                 int64_t* num_pairs_host, void* workspace, hipStream_t stream);
+
+/*
+ * fs_sort (Sec. 3.1: blending runs over depth-sorted surfels).  Stable LSD
+ * radix sort (8-bit digits, single-pass "onesweep" passes) of the first P =
+ * *num_pairs_dev pairs, by key, over 32 + ceil(log2 total_tiles) key bits;
+ * equal keys keep emission order (surfel index order).  Result in place in
+ * keys/vals.  tile_ranges (out, 2 * total_tiles uint32) receives [start, end)
+ * of every tile's run (0, 0 if empty).  num_pairs_hint >= 0 is the host's
+ * copy of P, used only to size the launch; pass -1 to size by capacity.
+ */
+fs_status fs_sort(uint64_t* keys, uint32_t* vals, int64_t pair_capacity, const int64_t* num_pairs_dev,
+                  int64_t num_pairs_hint, int64_t total_tiles, uint32_t* tile_ranges, void* workspace,
+                  hipStream_t stream);
+
+/*
+ * fs_render_forward (Sec. 3.1 Eq. 2; Sec. 3.4).  Per pixel, walks its tile's
+ * sorted list front to back:
+ *   (u, v) = ray-splat intersection; alpha = min(alpha_max, o exp(-(u^2+v^2)/2));
+ *   skip if alpha < alpha_min; stop before a surfel with T (1 - alpha) < t_stop;
+ *   w = alpha T; F += w c; T *= 1 - alpha; with topk = K > 0 stop after the
+ *   K-th blended surfel (Top-K hard selection, selected set = first K
+ *   contributors in depth order, weights = transmittance).
+ * Math in float32 (features read as float32 or bfloat16).
+ *   out_feat   out, total_pixels x C float32 (pixel-major, channels contiguous)
+ *   out_T      out, total_pixels float32 final transmittance
+ *   out_n      out, total_pixels int32 number of blended surfels
+ *   out_last   optional out, total_pixels int32: list position of the last
+ *              blended surfel, -1 if none (needed by fs_render_backward)
+ *   out_idx    optional out, total_pixels x topk int32 record indices of the
+ *              blended surfels front to back, -1 padded (topk > 0 only)
+ *   counters   optional in/out, 4 uint64 added to: [0] list entries walked
+ *              (over all blocks), [1] feature rows fetched (one per block and
+ *              used entry), [2] blended (pixel, surfel) pairs, [3] blocks run
+ */
+fs_status fs_render_forward(const void* records, const uint32_t* vals, const uint32_t* tile_ranges, const void* feats,
+                            int32_t C, int64_t n, const fs_camera* cams_dev, int32_t num_views, int64_t total_tiles,
+                            const fs_opts* opts, float* out_feat, float* out_T, int32_t* out_n, int32_t* out_last,
+                            int32_t* out_idx, uint64_t* counters, void* workspace, hipStream_t stream);
+
+/*
+ * fs_render_backward.  Given dL/dF (grad_feat, total_pixels x C float32) for
+ * the image fs_render_forward produced with the same inputs, accumulates
+ * (adds to) the gradients of L w.r.t. means (N x 3), scales (N x 2), quats
+ * (N x 4, w.r.t. the raw quaternion), opacity (N) and feats (N x C, float32
+ * even for bfloat16 storage).  Gradient buffers must be zeroed by the caller.
+ * The blend's discrete choices (accepted surfels, stopping points, the Top-K
+ * set, the alpha clamp) are held fixed, so only the selected surfels receive
+ * gradient.  grad_records is caller scratch of num_views * n *
+ * FS_GRAD_RECORD_FLOATS floats (zeroed by this call).
+ */
+fs_status fs_render_backward(const float* means, const float* scales, const float* quats, const float* opacity,
+                             const void* records, const uint32_t* vals, const uint32_t* tile_ranges,
+                             const void* feats, int32_t C, int64_t n, const fs_camera* cams_dev, int32_t num_views,
+                             int64_t total_tiles, const fs_opts* opts, const float* out_T, const int32_t* out_n,
+                             const int32_t* out_last, const float* grad_feat, float* grad_records, float* grad_means,
+                             float* grad_scales, float* grad_quats, float* grad_opacity, float* grad_feats,
+                             void* workspace, hipStream_t stream);
+
+/* Human-readable name of a status code (static storage). */
+const char* fs_status_string(fs_status status);
+
+/* The last HIP error code a call of this thread turned into FS_ERR_HIP. */
+int32_t fs_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTSEGSIM_H */

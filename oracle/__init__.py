@@ -36,9 +36,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfso.so")
 
-ALPHA_MIN = 1.0 / 255.0
-ALPHA_MAX = 0.99
-T_STOP = 1e-4
+# The thresholds are float32 numbers (the renderer's parameters are float32);
+# the oracle uses their exact double values so both sides test the same bound.
+ALPHA_MIN = float(np.float32(1.0 / 255.0))
+ALPHA_MAX = float(np.float32(0.99))
+T_STOP = float(np.float32(1e-4))
 
 _lib = None
 

@@ -1,0 +1,512 @@
+// fs_internal.h -- device-side definitions shared by the rasterizer kernels.
+//
+// Geometry (Sec. 3.1 Eq. 1, Sec. 3.2): a surfel with centre p, tangent scales
+// (r_u, r_v) and tangent vectors t_u, t_v maps tangent coordinates u = (u, v, 1)
+// to homogeneous screen coordinates x' = T u with T = K [U | V | p_c],
+// U = r_u R t_u, V = r_v R t_v, p_c = R p + t (camera rows T1, T2, Tw).  The
+// ray of pixel point (x, y) meets the tangent plane at u ~ (T1 - x Tw) x
+// (T2 - y Tw) = adj(T) (x, y, 1), so (u, v) = (h0 / h2, h1 / h2) with
+// h = adj(T) (x, y, 1).  A pixel is in a surfel's footprint iff
+// u^2 + v^2 <= k^2 with k^2 = 2 ln(o / alpha_min), i.e. iff o f(u) >= alpha_min.
+//
+// Integer decisions (depth key, culling, footprint membership and therefore
+// tile sets) are taken in double precision with a fixed evaluation order and
+// no contraction (the library is built with -ffp-contract=off), so they are a
+// pure function of the float32 inputs.  The blend itself runs in float32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fastsegsim.h"
+
+#define FS_DEV __device__ __forceinline__
+
+// ---------------------------------------------------------------------------
+// Per (view, surfel) record written by preprocess, read by the renderers.
+// Coefficients of h relative to an anchor pixel centre (ax + .5, ay + .5):
+// h(px, py) = h_a + (px - ax) g_x + (py - ay) g_y, normalised so that h2 = 1 at
+// the projected surfel centre.  They are kept in double precision: for thin or
+// grazing surfels the short-axis coordinate u at a pixel L pixels from the
+// anchor along the long axis is a cancellation of terms of size L |grad u|, so
+// float32 coefficients would leave an absolute error of ~6e-8 L |grad u| in u.
+// ---------------------------------------------------------------------------
+struct __align__(16) FsRecord {
+    double h0, h1, h2;          // h at the anchor
+    double gx0, gx1, gx2;       // dh/dx
+    double gy0, gy1, gy2;       // dh/dy
+    double k2;                  // cutoff k^2 (-1: culled)
+    float o;                    // opacity
+    int16_t ax, ay;             // anchor pixel (view-local)
+    int16_t x0, x1, y0, y1;     // pixel bounding box of the footprint, clamped (x0 > x1: empty)
+};
+static_assert(sizeof(FsRecord) == FS_RECORD_BYTES, "record size");
+
+// ---------------------------------------------------------------------------
+// Double-precision projection.  The evaluation order below is the one the
+// depth key, culling and footprint decisions are defined with.
+// ---------------------------------------------------------------------------
+struct FsGeo {
+    double H[9];      // adj(T), row-major: h = H (x, y, 1)
+    double T[9];      // rows T1, T2, Tw
+    double k2;        // cutoff
+    double zc;        // camera depth of the centre
+    uint32_t zkey;    // float32 bits of zc
+};
+
+FS_DEV void fs_cross(const double a[3], const double b[3], double c[3]) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+FS_DEV double fs_dot(const double a[3], const double b[3]) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+
+FS_DEV bool fs_finite(double x) { return __builtin_isfinite(x); }
+
+// Tangent vectors t_u, t_v: columns 0 and 1 of the rotation of q = (w, x, y, z),
+// with the textbook factor 2 replaced by f = 2 / |q|^2 (equal to normalising q).
+FS_DEV void fs_tangents(double w, double x, double y, double z, double f, double tu[3], double tv[3]) {
+    tu[0] = 1.0 - f * (y * y + z * z);
+    tu[1] = f * (x * y + w * z);
+    tu[2] = f * (x * z - w * y);
+    tv[0] = f * (x * y - w * z);
+    tv[1] = 1.0 - f * (x * x + z * z);
+    tv[2] = f * (y * z + w * x);
+}
+
+struct FsFrame {
+    double tu[3], tv[3], U[3], V[3], pc[3];
+    double f;
+};
+
+// Camera-space frame of a surfel.  Returns false for non-finite input, a zero
+// quaternion or a non-positive scale.
+FS_DEV bool fs_frame(const float* pm, const float* ps, const float* pq, const fs_camera& cam, FsFrame& fr) {
+    const double p0 = pm[0], p1 = pm[1], p2 = pm[2];
+    const double s0 = ps[0], s1 = ps[1];
+    const double w = pq[0], x = pq[1], y = pq[2], z = pq[3];
+    if (!fs_finite(p0) || !fs_finite(p1) || !fs_finite(p2) || !fs_finite(s0) || !fs_finite(s1) || !fs_finite(w) ||
+        !fs_finite(x) || !fs_finite(y) || !fs_finite(z))
+        return false;
+    const double qq = ((w * w + x * x) + y * y) + z * z;
+    if (!(qq > 0.0)) return false;
+    if (!(s0 > 0.0) || !(s1 > 0.0)) return false;
+    fr.f = 2.0 / qq;
+    fs_tangents(w, x, y, z, fr.f, fr.tu, fr.tv);
+    const double p[3] = {p0, p1, p2};
+    for (int r = 0; r < 3; ++r) {
+        const double R0 = cam.R[3 * r], R1 = cam.R[3 * r + 1], R2 = cam.R[3 * r + 2];
+        fr.U[r] = s0 * ((R0 * fr.tu[0] + R1 * fr.tu[1]) + R2 * fr.tu[2]);
+        fr.V[r] = s1 * ((R0 * fr.tv[0] + R1 * fr.tv[1]) + R2 * fr.tv[2]);
+        fr.pc[r] = ((R0 * p[0] + R1 * p[1]) + R2 * p[2]) + (double)cam.t[r];
+    }
+    return true;
+}
+
+// T = K [U | V | p_c] (rows T1, T2, Tw) and H = adj(T) with columns
+// T2 x Tw, Tw x T1, T1 x T2.
+FS_DEV void fs_screen(const fs_camera& cam, const FsFrame& fr, double T[9], double H[9]) {
+    const double fx = cam.fx, fy = cam.fy, cx = cam.cx, cy = cam.cy;
+    const double M0[3] = {fr.U[0], fr.V[0], fr.pc[0]};
+    const double M1[3] = {fr.U[1], fr.V[1], fr.pc[1]};
+    const double M2[3] = {fr.U[2], fr.V[2], fr.pc[2]};
+    for (int c = 0; c < 3; ++c) {
+        T[c] = fx * M0[c] + cx * M2[c];
+        T[3 + c] = fy * M1[c] + cy * M2[c];
+        T[6 + c] = M2[c];
+    }
+    double a[3], b[3], c1[3];
+    fs_cross(T + 3, T + 6, a);
+    fs_cross(T + 6, T, b);
+    fs_cross(T, T + 3, c1);
+    for (int r = 0; r < 3; ++r) {
+        H[3 * r] = a[r];
+        H[3 * r + 1] = b[r];
+        H[3 * r + 2] = c1[r];
+    }
+}
+
+// Full projection with culling: non-finite input, |q| = 0, scale <= 0, centre
+// depth <= z_near, o <= alpha_min, cutoff disk reaching depth <= z_near, or
+// edge-on (|n . p_c| <= 1e-6 |p_c|).
+FS_DEV bool fs_project(const float* pm, const float* ps, const float* pq, float opac, const fs_camera& cam,
+                       double alpha_min, FsGeo& g) {
+    FsFrame fr;
+    g.zkey = 0;
+    g.k2 = -1.0;
+    if (!fs_frame(pm, ps, pq, cam, fr)) return false;
+    const double o = opac;
+    if (!fs_finite(o)) return false;
+    g.zc = fr.pc[2];
+    g.zkey = __float_as_uint((float)fr.pc[2]);
+    const double zn = cam.z_near;
+    if (!(fr.pc[2] > zn)) return false;
+    if (!(o > alpha_min)) return false;
+    const double k2 = 2.0 * log(o / alpha_min);
+    const double dz = fr.pc[2] - zn;
+    if (dz * dz <= k2 * (fr.U[2] * fr.U[2] + fr.V[2] * fr.V[2])) return false;
+    double nrm[3];
+    fs_cross(fr.U, fr.V, nrm);
+    const double det = fs_dot(nrm, fr.pc);
+    if (det * det <= ((fs_dot(fr.U, fr.U) * fs_dot(fr.V, fr.V)) * fs_dot(fr.pc, fr.pc)) * 1e-12) return false;
+    fs_screen(cam, fr, g.T, g.H);
+    g.k2 = k2;
+    return true;
+}
+
+// The footprint predicate at pixel (px, py): u^2 + v^2 <= k^2 with
+// (u, v) = (h0 / h2, h1 / h2), h = H (px + .5, py + .5, 1).
+FS_DEV bool fs_pixel_in(const double H[9], double k2, int px, int py) {
+    const double x = (double)px + 0.5, y = (double)py + 0.5;
+    const double h0 = (H[0] * x + H[1] * y) + H[2];
+    const double h1 = (H[3] * x + H[4] * y) + H[5];
+    const double h2 = (H[6] * x + H[7] * y) + H[8];
+    if (h2 == 0.0) return false;
+    const double u = h0 / h2, v = h1 / h2;
+    return u * u + v * v <= k2;
+}
+
+// ---------------------------------------------------------------------------
+// Screen conic of the cutoff circle, relative to an anchor pixel centre:
+// q(dx, dy) = A dx^2 + 2B dx dy + C dy^2 + 2D dx + 2E dy + F <= 0 with
+// (x, y) = (ax + .5 + dx, ay + .5 + dy) -- the AccuTile quadratic of Sec. 3.2.
+// ---------------------------------------------------------------------------
+struct FsConic {
+    double A, B, C, D, E, F;
+    int ax, ay;
+};
+
+FS_DEV void fs_conic(const double H[9], double k2, int ax, int ay, FsConic& q) {
+    const double xa = (double)ax + 0.5, ya = (double)ay + 0.5;
+    const double a0 = H[0], a1 = H[3], a2 = H[6];
+    const double b0 = H[1], b1 = H[4], b2 = H[7];
+    const double c0 = (H[0] * xa + H[1] * ya) + H[2];
+    const double c1 = (H[3] * xa + H[4] * ya) + H[5];
+    const double c2 = (H[6] * xa + H[7] * ya) + H[8];
+    q.A = (a0 * a0 + a1 * a1) - k2 * (a2 * a2);
+    q.B = (a0 * b0 + a1 * b1) - k2 * (a2 * b2);
+    q.C = (b0 * b0 + b1 * b1) - k2 * (b2 * b2);
+    q.D = (a0 * c0 + a1 * c1) - k2 * (a2 * c2);
+    q.E = (b0 * c0 + b1 * c1) - k2 * (b2 * c2);
+    q.F = (c0 * c0 + c1 * c1) - k2 * (c2 * c2);
+    q.ax = ax;
+    q.ay = ay;
+}
+
+// Continuous extent of the ellipse (anchor-relative): dx in [x0, x1], dy in
+// [y0, y1].  Returns false if the conic is not a bounded ellipse.
+FS_DEV bool fs_conic_extent(const FsConic& q, double e[4]) {
+    const double det = q.A * q.C - q.B * q.B;
+    if (!(q.A > 0.0) || !(q.C > 0.0) || !(det > 0.0)) return false;
+    const double bx = q.B * q.E - q.C * q.D, by = q.B * q.D - q.A * q.E;
+    double rx = bx * bx + det * (q.E * q.E - q.C * q.F);
+    double ry = by * by + det * (q.D * q.D - q.A * q.F);
+    rx = rx > 0.0 ? rx : 0.0;
+    ry = ry > 0.0 ? ry : 0.0;
+    const double sx = sqrt(rx), sy = sqrt(ry);
+    e[0] = (bx - sx) / det;
+    e[1] = (bx + sx) / det;
+    e[2] = (by - sy) / det;
+    e[3] = (by + sy) / det;
+    return fs_finite(e[0]) && fs_finite(e[1]) && fs_finite(e[2]) && fs_finite(e[3]);
+}
+
+// Surfel footprint in pixel space: the exact predicate (H, k2) plus the
+// anchored conic, used to enumerate the footprint line by line.
+struct FsFootprint {
+    double H[9];
+    double k2;
+    FsConic q;
+    int px0, px1, py0, py1;   // candidate pixel range (inclusive), clamped to the image
+};
+
+FS_DEV int fs_clampi(long long v, int lo, int hi) { return (int)(v < lo ? lo : (v > hi ? hi : v)); }
+
+// Build the footprint: anchor at the pixel containing the projected centre
+// (clamped to the image), conic, and the candidate pixel range (conic extent
+// widened by one pixel).  Returns false if no pixel can be inside.
+FS_DEV bool fs_footprint(const FsGeo& g, int W, int Hh, FsFootprint& fp) {
+    for (int j = 0; j < 9; ++j) fp.H[j] = g.H[j];
+    fp.k2 = g.k2;
+    const double mx = g.T[2] / g.T[8], my = g.T[5] / g.T[8];
+    const double lim = 1.0e6;
+    const double cmx = mx < -lim ? -lim : (mx > lim ? lim : mx);
+    const double cmy = my < -lim ? -lim : (my > lim ? lim : my);
+    const int ax = fs_clampi((long long)floor(cmx), 0, W - 1);
+    const int ay = fs_clampi((long long)floor(cmy), 0, Hh - 1);
+    fs_conic(fp.H, fp.k2, ax, ay, fp.q);
+    double e[4];
+    if (!fs_conic_extent(fp.q, e)) {
+        fp.px0 = 0;
+        fp.px1 = W - 1;
+        fp.py0 = 0;
+        fp.py1 = Hh - 1;
+        return true;
+    }
+    const double big = 4.0e6;
+    for (int j = 0; j < 4; ++j) e[j] = e[j] < -big ? -big : (e[j] > big ? big : e[j]);
+    // pixel centre px + .5 = ax + .5 + dx  ->  px = ax + dx
+    fp.px0 = fs_clampi((long long)ceil(e[0]) + ax - 1, 0, W - 1);
+    fp.px1 = fs_clampi((long long)floor(e[1]) + ax + 1, 0, W - 1);
+    fp.py0 = fs_clampi((long long)ceil(e[2]) + ay - 1, 0, Hh - 1);
+    fp.py1 = fs_clampi((long long)floor(e[3]) + ay + 1, 0, Hh - 1);
+    if ((long long)floor(e[1]) + ax + 1 < 0 || (long long)ceil(e[0]) + ax - 1 > W - 1) return false;
+    if ((long long)floor(e[3]) + ay + 1 < 0 || (long long)ceil(e[2]) + ay - 1 > Hh - 1) return false;
+    return fp.px0 <= fp.px1 && fp.py0 <= fp.py1;
+}
+
+// Pixels of one line inside the footprint.  Row mode (rows = true): line is
+// pixel row `l`, the result [lo, hi] are pixel columns.  Column mode: line is
+// pixel column `l`, result are pixel rows.  The quadratic (the AccuTile
+// equation of Sec. 3.2) gives the interval; endpoint pixels whose centres lie
+// within 1e-4 px of the conic are re-decided with the exact predicate, so the
+// result equals the per-pixel definition.  Returns false if the line is empty.
+FS_DEV bool fs_line_interval(const FsFootprint& fp, bool rows, int l, int lo_lim, int hi_lim, int& lo, int& hi) {
+    const FsConic& q = fp.q;
+    // along-line coordinate s, across-line offset d (both anchor-relative)
+    double a, b, c, d;
+    int anchor_s;
+    if (rows) {
+        d = (double)(l - q.ay);
+        a = q.A;
+        b = q.B * d + q.D;
+        c = (q.C * d + 2.0 * q.E) * d + q.F;
+        anchor_s = q.ax;
+    } else {
+        d = (double)(l - q.ax);
+        a = q.C;
+        b = q.B * d + q.E;
+        c = (q.A * d + 2.0 * q.D) * d + q.F;
+        anchor_s = q.ay;
+    }
+    if (!(a > 0.0)) {
+        // degenerate in floating point: decide every pixel of the line
+        lo = hi_lim + 1;
+        hi = lo_lim - 1;
+        for (int s = lo_lim; s <= hi_lim; ++s) {
+            const bool in = rows ? fs_pixel_in(fp.H, fp.k2, s, l) : fs_pixel_in(fp.H, fp.k2, l, s);
+            if (in) {
+                lo = lo < s ? lo : s;
+                hi = s;
+            }
+        }
+        return lo <= hi;
+    }
+    const double eps = 1e-4;
+    const double disc = b * b - a * c;
+    auto pin = [&](int s) -> bool { return rows ? fs_pixel_in(fp.H, fp.k2, s, l) : fs_pixel_in(fp.H, fp.k2, l, s); };
+    if (disc < 0.0) {
+        // empty unless the line is tangent within rounding: test the pixel
+        // nearest the vertex and grow from it
+        if (-disc > 1e-8 * (b * b + fabs(a * c))) return false;
+        const double sv = -b / a;
+        if (!(fabs(sv) < 4.0e6)) return false;
+        const int s0 = (int)rint(sv) + anchor_s;
+        if (s0 < lo_lim || s0 > hi_lim || !pin(s0)) return false;
+        lo = hi = s0;
+        while (lo > lo_lim && pin(lo - 1)) --lo;
+        while (hi < hi_lim && pin(hi + 1)) ++hi;
+        return true;
+    }
+    const double sq = sqrt(disc);
+    // roots s1 <= s2 (numerically stable form)
+    double s1, s2;
+    if (b >= 0.0) {
+        const double t = -(b + sq);
+        s1 = t / a;
+        s2 = (t != 0.0) ? c / t : 0.0;
+    } else {
+        const double t = -b + sq;
+        s2 = t / a;
+        s1 = c / t;
+    }
+    if (s1 > s2) {
+        const double tmp = s1;
+        s1 = s2;
+        s2 = tmp;
+    }
+    if (!(s1 > -4.0e6)) s1 = -4.0e6;
+    if (!(s2 < 4.0e6)) s2 = 4.0e6;
+    // centres strictly inside: s in [ceil(s1), floor(s2)]
+    const double cs1 = ceil(s1), fs2 = floor(s2);
+    long long L = (long long)cs1 + anchor_s, Hi = (long long)fs2 + anchor_s;
+    // re-decide endpoints within eps of the conic
+    if (cs1 - s1 < eps) {                     // first centre barely inside
+        if (L >= lo_lim && L <= hi_lim && !pin((int)L)) ++L;
+    } else if (1.0 - (cs1 - s1) < eps) {      // centre before it barely outside
+        if (L - 1 >= lo_lim && L - 1 <= hi_lim && pin((int)(L - 1))) --L;
+    }
+    if (s2 - fs2 < eps) {
+        if (Hi >= lo_lim && Hi <= hi_lim && !pin((int)Hi)) --Hi;
+    } else if (1.0 - (s2 - fs2) < eps) {
+        if (Hi + 1 >= lo_lim && Hi + 1 <= hi_lim && pin((int)(Hi + 1))) ++Hi;
+    }
+    if (L < lo_lim) L = lo_lim;
+    if (Hi > hi_lim) Hi = hi_lim;
+    if (L > Hi) return false;
+    lo = (int)L;
+    hi = (int)Hi;
+    return true;
+}
+
+// Enumerate the tiles of the footprint (SnugBox traversal: lines run along the
+// shorter side of the pixel range, Sec. 3.2).  For every tile line (a tile
+// row in row mode, a tile column in column mode) the tile spans of its pixel
+// lines are OR-ed into a 64-bit mask over a window of at most 64 tiles, then
+// visit(tx, ty) is called for each tile of the union, in increasing order.
+template <class Visit>
+FS_DEV void fs_sweep_tiles(const FsFootprint& fp, int S, Visit&& visit) {
+    const bool rows = (fp.py1 - fp.py0) <= (fp.px1 - fp.px0);
+    const int l0 = rows ? fp.py0 : fp.px0, l1 = rows ? fp.py1 : fp.px1;      // lines
+    const int s0 = rows ? fp.px0 : fp.py0, s1 = rows ? fp.px1 : fp.py1;      // along-line range
+    const int ts0 = s0 / S, ts1 = s1 / S;
+    for (int wbase = ts0; wbase <= ts1; wbase += 64) {
+        for (int tl = l0 / S; tl <= l1 / S; ++tl) {
+            uint64_t mask = 0;
+            const int la = tl * S > l0 ? tl * S : l0;
+            const int lb = tl * S + S - 1 < l1 ? tl * S + S - 1 : l1;
+            for (int l = la; l <= lb; ++l) {
+                int lo, hi;
+                if (!fs_line_interval(fp, rows, l, s0, s1, lo, hi)) continue;
+                int t1 = lo / S - wbase, t2 = hi / S - wbase;
+                if (t2 < 0 || t1 > 63) continue;
+                t1 = t1 < 0 ? 0 : t1;
+                t2 = t2 > 63 ? 63 : t2;
+                const uint64_t hiBits = (t2 == 63) ? ~0ull : ((1ull << (t2 + 1)) - 1ull);
+                mask |= hiBits & ~((1ull << t1) - 1ull);
+            }
+            while (mask) {
+                const int b = __builtin_ctzll(mask);
+                mask &= mask - 1ull;
+                const int ts = wbase + b;
+                if (rows)
+                    visit(ts, tl);
+                else
+                    visit(tl, ts);
+            }
+        }
+    }
+}
+
+// Tiles of the square circumscribing the ellipse (centre +- semi-major axis):
+// the bounding-box assignment used as the baseline of the tile ablation.
+FS_DEV bool fs_bbox_tiles(const FsFootprint& fp, int W, int Hh, int S, int& tx0, int& tx1, int& ty0, int& ty1) {
+    const FsConic& q = fp.q;
+    const double det = q.A * q.C - q.B * q.B;
+    if (!(q.A > 0.0) || !(q.C > 0.0) || !(det > 0.0)) {
+        tx0 = fp.px0 / S;
+        tx1 = fp.px1 / S;
+        ty0 = fp.py0 / S;
+        ty1 = fp.py1 / S;
+        return true;
+    }
+    const double xc = (q.B * q.E - q.C * q.D) / det, yc = (q.B * q.D - q.A * q.E) / det;
+    const double f0 = -((q.D * xc + q.E * yc) + q.F);
+    if (!(f0 > 0.0)) return false;
+    const double hm = 0.5 * (q.A + q.C), dd = 0.5 * (q.A - q.C);
+    const double lmin = hm - sqrt(dd * dd + q.B * q.B);
+    if (!(lmin > 0.0)) return false;
+    const double r = sqrt(f0 / lmin) * (1.0 + 1e-9) + 1e-6;
+    const double cx = xc + q.ax, cy = yc + q.ay;     // in pixel-index units (centre at +.5)
+    const long long x0 = (long long)ceil(cx - r), x1 = (long long)floor(cx + r);
+    const long long y0 = (long long)ceil(cy - r), y1 = (long long)floor(cy + r);
+    if (x1 < 0 || y1 < 0 || x0 > W - 1 || y0 > Hh - 1 || x0 > x1 || y0 > y1) return false;
+    tx0 = fs_clampi(x0, 0, W - 1) / S;
+    tx1 = fs_clampi(x1, 0, W - 1) / S;
+    ty0 = fs_clampi(y0, 0, Hh - 1) / S;
+    ty1 = fs_clampi(y1, 0, Hh - 1) / S;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Response of a record at pixel offset (dx, dy) from its anchor: (u, v) and
+// d2 = u^2 + v^2 in double precision (fused multiply-adds; 1/h2 from the
+// hardware reciprocal refined by one Newton step).  Shared by the forward and
+// backward renderers so both take identical accept decisions.
+// ---------------------------------------------------------------------------
+struct FsResp {
+    double u, v, d2, rh;   // tangent coordinates, u^2 + v^2, 1 / h2
+};
+
+FS_DEV FsResp fs_response(const FsRecord& r, double dx, double dy) {
+    FsResp o;
+    const double h0 = fma(dy, r.gy0, fma(dx, r.gx0, r.h0));
+    const double h1 = fma(dy, r.gy1, fma(dx, r.gx1, r.h1));
+    const double h2 = fma(dy, r.gy2, fma(dx, r.gx2, r.h2));
+    double rh = __builtin_amdgcn_rcp(h2);
+    rh = fma(rh, fma(-h2, rh, 1.0), rh);
+    o.rh = rh;
+    o.u = h0 * rh;
+    o.v = h1 * rh;
+    o.d2 = fma(o.u, o.u, o.v * o.v);
+    return o;
+}
+
+// Record index -> surfel index for record r = v * n + i.
+FS_DEV int64_t fs_surfel_of(int64_t rec, int64_t n) { return rec % n; }
+
+// View of a global tile id (binary search over tile offsets; num_views is small).
+FS_DEV int fs_view_of_tile(const fs_camera* cams, int num_views, int64_t tile) {
+    int lo = 0, hi = num_views - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)cams[mid].tile_offset <= tile)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch helpers implemented in the .hip files.
+// ---------------------------------------------------------------------------
+struct FsWorkspace {
+    // bin (scan + emit)
+    uint64_t* scan_status;
+    uint32_t* scan_ticket;
+    int64_t scan_parts;
+    // sort
+    uint32_t* hist;          // npass x 256
+    uint32_t* digit_off;     // npass x 256
+    uint32_t* sort_status;   // npass x parts x 256
+    uint32_t* sort_ticket;   // npass
+    int32_t* sort_ctrl;      // [0..npass): source buffer of each pass (-1: skipped); [npass]: final buffer
+    uint64_t* keys_alt;
+    uint32_t* vals_alt;
+    int64_t sort_parts;
+    int npass;
+    // render
+    uint32_t* render_ticket;
+};
+
+bool fs_workspace_layout(void* base, int64_t n, int32_t num_views, int64_t total_tiles, int64_t pair_capacity,
+                         const fs_opts* opts, FsWorkspace* ws, size_t* bytes);
+
+hipError_t fs_launch_preprocess(const float* means, const float* scales, const float* quats, const float* opacity,
+                                int64_t n, const fs_camera* cams, int32_t num_views, const fs_opts& o,
+                                FsRecord* records, uint32_t* tiles_touched, hipStream_t s);
+
+hipError_t fs_launch_bin(const float* means, const float* scales, const float* quats, const float* opacity, int64_t n,
+                         const fs_camera* cams, int32_t num_views, const fs_opts& o, const uint32_t* tiles_touched,
+                         uint64_t* keys, uint32_t* vals, int64_t capacity, int64_t* num_pairs, const FsWorkspace& ws,
+                         hipStream_t s);
+
+hipError_t fs_launch_sort(uint64_t* keys, uint32_t* vals, int64_t capacity, const int64_t* num_pairs, int64_t hint,
+                          int64_t total_tiles, uint32_t* ranges, const FsWorkspace& ws, hipStream_t s);
+
+hipError_t fs_launch_render_forward(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges,
+                                    const void* feats, int C, int64_t n, const fs_camera* cams, int num_views,
+                                    int64_t total_tiles, const fs_opts& o, float* out_feat, float* out_T,
+                                    int32_t* out_n, int32_t* out_last, int32_t* out_idx, uint64_t* counters,
+                                    const FsWorkspace& ws, hipStream_t s);
+
+hipError_t fs_launch_render_backward(const float* means, const float* scales, const float* quats,
+                                     const float* opacity, const FsRecord* records, const uint32_t* vals,
+                                     const uint32_t* ranges, const void* feats, int C, int64_t n,
+                                     const fs_camera* cams, int num_views, int64_t total_tiles, const fs_opts& o,
+                                     const float* out_T, const int32_t* out_n, const int32_t* out_last,
+                                     const float* grad_feat, float* grad_records, float* grad_means,
+                                     float* grad_scales, float* grad_quats, float* grad_opacity, float* grad_feats,
+                                     const FsWorkspace& ws, hipStream_t s);

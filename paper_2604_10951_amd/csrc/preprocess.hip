@@ -1,0 +1,88 @@
+// preprocess.hip -- per (view, surfel) projection, culling, record and tile
+// count (Sec. 3.1 Eq. 1; Sec. 3.2 conic, SnugBox and AccuTile).
+//
+// One lane per (view, surfel); 256-lane workgroups, grid.y = view.  Geometry
+// runs in double precision (gfx950 runs fp64 at the fp32 vector rate), so the
+// tile count is the exact per-pixel footprint count.
+#include "fs_internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ void __launch_bounds__(kThreads)
+preprocess_kernel(const float* __restrict__ means, const float* __restrict__ scales, const float* __restrict__ quats,
+                  const float* __restrict__ opacity, int64_t n, const fs_camera* __restrict__ cams, fs_opts o,
+                  FsRecord* __restrict__ records, uint32_t* __restrict__ tiles_touched) {
+    const int v = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const fs_camera cam = cams[v];
+    const int64_t r = (int64_t)v * n + i;
+    FsRecord rec;
+    rec.h0 = rec.h1 = rec.h2 = 0.0;
+    rec.gx0 = rec.gx1 = rec.gx2 = 0.0;
+    rec.gy0 = rec.gy1 = rec.gy2 = 0.0;
+    rec.k2 = -1.0;
+    rec.o = 0.f;
+    rec.ax = rec.ay = 0;
+    rec.x0 = 1;
+    rec.x1 = 0;
+    rec.y0 = 1;
+    rec.y1 = 0;
+    uint32_t count = 0;
+    FsGeo g;
+    const float op = opacity[i];
+    if (fs_project(means + 3 * i, scales + 2 * i, quats + 4 * i, op, cam, (double)o.alpha_min, g)) {
+        FsFootprint fp;
+        if (fs_footprint(g, cam.width, cam.height, fp)) {
+            const int S = o.tile;
+            if (o.tile_mode == FS_TILES_BBOX) {
+                int tx0, tx1, ty0, ty1;
+                if (fs_bbox_tiles(fp, cam.width, cam.height, S, tx0, tx1, ty0, ty1))
+                    count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+            } else {
+                fs_sweep_tiles(fp, S, [&](int, int) { ++count; });
+            }
+        }
+        if (count > 0) {
+            // render coefficients, anchored and normalised (h2 = 1 at the
+            // projected centre)
+            const double mx = g.T[2] / g.T[8], my = g.T[5] / g.T[8];
+            const double s = (g.H[6] * mx + g.H[7] * my) + g.H[8];
+            const double is = 1.0 / s;
+            const double xa = fp.q.ax + 0.5, ya = fp.q.ay + 0.5;
+            rec.h0 = ((g.H[0] * xa + g.H[1] * ya) + g.H[2]) * is;
+            rec.h1 = ((g.H[3] * xa + g.H[4] * ya) + g.H[5]) * is;
+            rec.h2 = ((g.H[6] * xa + g.H[7] * ya) + g.H[8]) * is;
+            rec.gx0 = g.H[0] * is;
+            rec.gx1 = g.H[3] * is;
+            rec.gx2 = g.H[6] * is;
+            rec.gy0 = g.H[1] * is;
+            rec.gy1 = g.H[4] * is;
+            rec.gy2 = g.H[7] * is;
+            rec.o = op;
+            rec.k2 = g.k2;
+            rec.ax = (int16_t)fp.q.ax;
+            rec.ay = (int16_t)fp.q.ay;
+            rec.x0 = (int16_t)fp.px0;
+            rec.x1 = (int16_t)fp.px1;
+            rec.y0 = (int16_t)fp.py0;
+            rec.y1 = (int16_t)fp.py1;
+        }
+    }
+    records[r] = rec;
+    tiles_touched[r] = count;
+}
+
+}  // namespace
+
+hipError_t fs_launch_preprocess(const float* means, const float* scales, const float* quats, const float* opacity,
+                                int64_t n, const fs_camera* cams, int32_t num_views, const fs_opts& o,
+                                FsRecord* records, uint32_t* tiles_touched, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    dim3 grid((unsigned)((n + kThreads - 1) / kThreads), (unsigned)num_views);
+    hipLaunchKernelGGL(preprocess_kernel, grid, dim3(kThreads), 0, s, means, scales, quats, opacity, n, cams, o,
+                       records, tiles_touched);
+    return hipGetLastError();
+}

@@ -1,0 +1,362 @@
+// render_fwd.hip -- per-pixel front-to-back blending of C-channel features,
+// full (Sec. 3.1 Eq. 2) or with Top-K hard selection (Sec. 3.4).
+//
+// Work decomposition.  A workgroup renders one render block (8x8 pixels per
+// wave; 1 wave = 8x8 block, 4 waves = 16x16 block) of a binning tile and one
+// chunk of at most 64*CPL channels.  The tile's depth-sorted list is walked in
+// batches of BG entries:
+//   1. stage: the BG records (64 B each) are copied to LDS;
+//   2. weights (lanes = pixels): every lane walks the batch in depth order for
+//      its pixel -- ray-splat (u, v), alpha, transmittance, the stop and Top-K
+//      tests -- and writes its blend weight w = alpha T per accepted entry to
+//      LDS plus a bit mask of accepted entries.  A wave skips entries whose
+//      footprint box misses its 8x8 pixels;
+//   3. fetch: the feature rows of entries accepted by any pixel of the block
+//      are loaded once, coalesced, into LDS (float32 or bfloat16 storage);
+//   4. accumulate (lanes = channels): for each of its 64 pixels (a static,
+//      unrolled loop, so the accumulators stay in VGPRs) a wave walks the
+//      accepted entries and adds w * c to CPL channels per lane: one FMA per
+//      channel per (pixel, contributor) with no idle lanes, and every LDS read
+//      is either a broadcast (w) or conflict-free (the row).
+// The block exits as soon as every pixel has stopped (T_stop, or K blended
+// surfels), which is where Top-K saves work.  Feature images are written
+// pixel-major (channels contiguous), 64*CPL*4 bytes per pixel per chunk.
+#include <type_traits>
+
+#include "fs_internal.h"
+
+namespace {
+
+FS_DEV float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+template <typename FT>
+FS_DEV float feat_to_f32(FT x);
+template <>
+FS_DEV float feat_to_f32<float>(float x) { return x; }
+template <>
+FS_DEV float feat_to_f32<uint16_t>(uint16_t x) { return bf16_to_f32(x); }
+
+FS_DEV uint32_t wave_or(uint32_t x) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) x |= __shfl_xor(x, d, 64);
+    return x;
+}
+
+struct BlockPos {
+    int view;
+    int x0, y0;      // block origin (view-local pixels)
+    int64_t tile;    // global tile id
+    bool valid;
+};
+
+FS_DEV BlockPos locate_block(int64_t b, int S, int RB, const fs_camera* cams, int num_views) {
+    BlockPos bp;
+    const int sb = S / RB;
+    const int64_t tile = b / (sb * sb);
+    const int sub = (int)(b % (sb * sb));
+    const int v = fs_view_of_tile(cams, num_views, tile);
+    const fs_camera& cam = cams[v];
+    const int tiles_x = (cam.width + S - 1) / S;
+    const int64_t local = tile - cam.tile_offset;
+    const int tx = (int)(local % tiles_x), ty = (int)(local / tiles_x);
+    bp.view = v;
+    bp.tile = tile;
+    bp.x0 = tx * S + (sub % sb) * RB;
+    bp.y0 = ty * S + (sub / sb) * RB;
+    bp.valid = bp.x0 < cam.width && bp.y0 < cam.height;
+    return bp;
+}
+
+// Bytes of a vector load of feature elements (16 B when C allows it).
+template <typename FT, bool VEC>
+struct RowVec {
+    static constexpr int kElems = VEC ? 16 / (int)sizeof(FT) : 1;
+};
+
+template <int CPL, typename FT, int WAVES, int BG, bool VEC>
+__global__ void __launch_bounds__(WAVES * 64)
+render_fwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restrict__ vals,
+                  const uint32_t* __restrict__ ranges, const FT* __restrict__ feats, int C, int64_t n,
+                  int64_t num_records, const fs_camera* __restrict__ cams, int num_views, int S, fs_opts o,
+                  float* __restrict__ out_feat, float* __restrict__ out_T, int32_t* __restrict__ out_n,
+                  int32_t* __restrict__ out_last, int32_t* __restrict__ out_idx, uint64_t* __restrict__ counters) {
+    constexpr int NT = WAVES * 64;
+    constexpr int kChunk = 64 * CPL;
+    constexpr int RB = WAVES == 1 ? 8 : 16;
+    constexpr int kQ = FS_RECORD_BYTES / 16;                 // float4 per record
+    constexpr int kRecSlots = (BG * kQ + NT - 1) / NT;       // record float4 per thread
+    constexpr int kVE = RowVec<FT, VEC>::kElems;             // feature elements per vector load
+
+    __shared__ FsRecord s_rec[BG];
+    __shared__ uint32_t s_recid[BG];
+    __shared__ __align__(16) FT s_feat[BG][kChunk];
+    __shared__ float s_w[WAVES][BG][64];
+    __shared__ uint32_t s_used;
+    __shared__ int s_active;
+    __shared__ int s_list[BG];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const BlockPos bp = locate_block(blockIdx.x, S, RB, cams, num_views);
+    if (!bp.valid) return;
+    const fs_camera& cam = cams[bp.view];
+    const int chunk = blockIdx.y;
+    const int c0 = chunk * kChunk;
+    const int clen = C - c0 < kChunk ? C - c0 : kChunk;
+    const int wx0 = bp.x0 + (WAVES == 1 ? 0 : (wave & 1) * 8);
+    const int wy0 = bp.y0 + (WAVES == 1 ? 0 : (wave >> 1) * 8);
+    const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
+    const bool inside = px < cam.width && py < cam.height;
+    const int64_t pix = cam.pixel_offset + (int64_t)py * cam.width + px;
+    const uint32_t start = ranges[2 * bp.tile], end = ranges[2 * bp.tile + 1];
+    const int K = o.topk;
+    const bool write_idx = out_idx != nullptr && chunk == 0 && K > 0;
+
+    double T = 1.0;
+    int cnt = 0;
+    int last = -1;
+    bool done = !inside;
+    float acc[64][CPL];
+#pragma unroll
+    for (int p = 0; p < 64; ++p)
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) acc[p][c] = 0.f;
+
+    const double t_stop = o.t_stop;
+    const float neg_half_log2e = -0.72134752044448170f;   // -log2(e) / 2
+    uint32_t walked = 0, fetched = 0;
+
+    // record prefetch registers (the next batch is loaded while this one runs)
+    float4 pre[kRecSlots];
+    uint32_t pre_rid[kRecSlots];
+    auto prefetch = [&](uint32_t b0) {
+#pragma unroll
+        for (int j = 0; j < kRecSlots; ++j) {
+            const int t = tid + j * NT;
+            const int e = t / kQ, q = t - e * kQ;
+            pre_rid[j] = 0xffffffffu;
+            pre[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (e < BG && b0 + (uint32_t)e < end) {
+                const uint32_t rid = vals[b0 + e];
+                pre_rid[j] = rid;
+                if ((int64_t)rid < num_records) pre[j] = reinterpret_cast<const float4*>(records + rid)[q];
+            }
+        }
+    };
+    if (start < end) prefetch(start);
+
+    for (uint32_t b0 = start; b0 < end; b0 += BG) {
+        const int nb = (int)(end - b0 < (uint32_t)BG ? end - b0 : (uint32_t)BG);
+        // 1. stage the prefetched records
+        if (tid == 0) {
+            s_used = 0u;
+            s_active = 0;
+        }
+#pragma unroll
+        for (int j = 0; j < kRecSlots; ++j) {
+            const int t = tid + j * NT;
+            const int e = t / kQ, q = t - e * kQ;
+            if (e < nb) {
+                float4 v4 = pre[j];
+                uint32_t rid = pre_rid[j];
+                if ((int64_t)rid >= num_records) {   // never happens for a well-formed list
+                    rid = 0u;
+                    v4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (q == 4) v4.w = __int_as_float((int)0xbff00000);   // k2 = -1: never accepted
+                    if (q == 5) v4.z = __int_as_float(1);                 // empty box
+                }
+                reinterpret_cast<float4*>(&s_rec[e])[q] = v4;
+                if (q == 0) s_recid[e] = rid;
+            }
+        }
+        __syncthreads();
+        if (b0 + BG < end) prefetch(b0 + BG);
+        // 2. weights, lanes = pixels
+        uint32_t mask = 0u;
+        if (!__all(done)) {
+            for (int e = 0; e < nb; ++e) {
+                const FsRecord& r = s_rec[e];
+                if (r.x1 < wx0 || r.x0 > wx0 + 7 || r.y1 < wy0 || r.y0 > wy0 + 7) continue;
+                if (!done) {
+                    const FsResp rs = fs_response(r, (double)(px - r.ax), (double)(py - r.ay));
+                    if (rs.d2 <= r.k2) {
+                        const float G = __builtin_amdgcn_exp2f(neg_half_log2e * (float)rs.d2);
+                        const float alpha = fminf(o.alpha_max, r.o * G);
+                        const double Tn = T * (1.0 - (double)alpha);
+                        if (Tn < t_stop) {
+                            done = true;
+                        } else {
+                            s_w[wave][e][lane] = (float)((double)alpha * T);
+                            mask |= 1u << e;
+                            T = Tn;
+                            if (write_idx) out_idx[pix * K + cnt] = (int32_t)s_recid[e];
+                            ++cnt;
+                            last = (int)(b0 + e);
+                            if (K > 0 && cnt == K) done = true;
+                        }
+                    }
+                }
+                if ((e & 7) == 7 && __all(done)) break;
+            }
+        }
+        const uint32_t wused = wave_or(mask);
+        const uint64_t active_px = __ballot(mask != 0u);
+        const bool wactive = !__all(done);
+        if (lane == 0) {
+            if (wused) atomicOr(&s_used, wused);
+            if (wactive) atomicAdd(&s_active, 1);
+        }
+        __syncthreads();
+        const uint32_t used = s_used;
+        const int active = s_active;   // latched: wave 0 re-zeroes both at the next batch
+        const int nu = __popc(used);
+        if (tid < BG && ((used >> tid) & 1u)) s_list[__popc(used & ((1u << tid) - 1u))] = tid;
+        walked += (uint32_t)nb;
+        fetched += (uint32_t)nu;
+        __syncthreads();
+        // 3. fetch the feature rows of accepted entries: every load is issued
+        //    before the first LDS store
+        if (VEC) {
+            // direct global -> LDS loads, 16 B per lane, rows packed in the
+            // order of the compacted list (row j of the batch at s_feat[j])
+            constexpr int kRowBytes = kChunk * (int)sizeof(FT);
+            constexpr int kLanesPerRow = kRowBytes / 16;
+            constexpr int kRowsPerInst = 64 / kLanesPerRow;
+            const int ninst = (nu + kRowsPerInst - 1) / kRowsPerInst;
+            const int lrow = lane / kLanesPerRow, lcol = lane - lrow * kLanesPerRow;
+            for (int i = wave; i < ninst; i += WAVES) {
+                const int row = i * kRowsPerInst + lrow;
+                if (row < nu && lcol * kVE < clen) {
+                    const int64_t sidx = fs_surfel_of(s_recid[s_list[row]], n);
+                    const FT* src = feats + sidx * C + c0 + lcol * kVE;
+                    __builtin_amdgcn_global_load_lds(
+                        (const void*)src, (__attribute__((address_space(3))) void*)&s_feat[i * kRowsPerInst][0], 16,
+                        0, 0);
+                }
+            }
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        } else {
+            for (int t = tid; t < nu * kChunk; t += NT) {
+                const int j = t / kChunk, c = t - j * kChunk;
+                if (c < clen) {
+                    const int e = s_list[j];
+                    const int64_t sidx = fs_surfel_of(s_recid[e], n);
+                    s_feat[j][c] = feats[sidx * C + c0 + c];
+                }
+            }
+        }
+        __syncthreads();
+        // 4. accumulate, lanes = channels
+#pragma unroll
+        for (int p = 0; p < 64; ++p) {
+            if ((active_px >> p) & 1ull) {
+                uint32_t m = __builtin_amdgcn_readlane(mask, p);
+                while (m) {
+                    const int e = __builtin_ctz(m);
+                    m &= m - 1u;
+                    const int j = __popc(used & ((1u << e) - 1u));   // row slot of entry e
+                    const float w = s_w[wave][e][p];
+                    if (CPL == 2 && sizeof(FT) == 4) {
+                        const float2 f = *reinterpret_cast<const float2*>(&s_feat[j][lane * 2]);
+                        acc[p][0] = fmaf(w, f.x, acc[p][0]);
+                        acc[p][CPL - 1] = fmaf(w, f.y, acc[p][CPL - 1]);
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < CPL; ++c)
+                            acc[p][c] = fmaf(w, feat_to_f32(s_feat[j][lane * CPL + c]), acc[p][c]);
+                    }
+                }
+            }
+        }
+        if (active == 0) break;
+    }
+
+    if (counters != nullptr && chunk == 0) {
+        int c = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) c += __shfl_xor(c, d, 64);
+        if (lane == 0) atomicAdd((unsigned long long*)&counters[2], (unsigned long long)c);
+        if (tid == 0) {
+            atomicAdd((unsigned long long*)&counters[0], (unsigned long long)walked);
+            atomicAdd((unsigned long long*)&counters[1], (unsigned long long)fetched);
+            atomicAdd((unsigned long long*)&counters[3], 1ull);
+        }
+    }
+    if (chunk == 0 && inside) {
+        out_T[pix] = (float)T;
+        out_n[pix] = cnt;
+        if (out_last) out_last[pix] = last;
+        if (write_idx)
+            for (int j = cnt; j < K; ++j) out_idx[pix * K + j] = -1;
+    }
+    const int cl = lane * CPL;
+#pragma unroll
+    for (int p = 0; p < 64; ++p) {
+        const int qx = wx0 + (p & 7), qy = wy0 + (p >> 3);
+        if (qx < cam.width && qy < cam.height) {
+            float* dst = out_feat + (cam.pixel_offset + (int64_t)qy * cam.width + qx) * C + c0 + cl;
+            if (CPL == 2 && cl + 1 < clen && ((C & 1) == 0)) {
+                *reinterpret_cast<float2*>(dst) = make_float2(acc[p][0], acc[p][CPL - 1]);
+            } else {
+#pragma unroll
+                for (int c = 0; c < CPL; ++c)
+                    if (cl + c < clen) dst[c] = acc[p][c];
+            }
+        }
+    }
+}
+
+template <int CPL, typename FT, int WAVES, int BG>
+hipError_t launch(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges, const void* feats, int C,
+                  int64_t n, const fs_camera* cams, int num_views, int64_t total_tiles, const fs_opts& o,
+                  float* out_feat, float* out_T, int32_t* out_n, int32_t* out_last, int32_t* out_idx,
+                  uint64_t* counters, hipStream_t s) {
+    constexpr int RB = WAVES == 1 ? 8 : 16;
+    const int sb = o.tile / RB;
+    const int64_t blocks = total_tiles * sb * sb;
+    const int chunks = (C + 64 * CPL - 1) / (64 * CPL);
+    const bool vec = (C % (16 / (int)sizeof(FT))) == 0;
+    dim3 grid((unsigned)blocks, (unsigned)chunks);
+    if (vec)
+        hipLaunchKernelGGL((render_fwd_kernel<CPL, FT, WAVES, BG, true>), grid, dim3(WAVES * 64), 0, s, records, vals,
+                           ranges, static_cast<const FT*>(feats), C, n, n * num_views, cams, num_views, o.tile, o,
+                           out_feat, out_T, out_n, out_last, out_idx, counters);
+    else
+        hipLaunchKernelGGL((render_fwd_kernel<CPL, FT, WAVES, BG, false>), grid, dim3(WAVES * 64), 0, s, records,
+                           vals, ranges, static_cast<const FT*>(feats), C, n, n * num_views, cams, num_views, o.tile,
+                           o, out_feat, out_T, out_n, out_last, out_idx, counters);
+    return hipGetLastError();
+}
+
+template <int CPL, typename FT>
+hipError_t launch_waves(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges, const void* feats,
+                        int C, int64_t n, const fs_camera* cams, int num_views, int64_t total_tiles,
+                        const fs_opts& o, float* out_feat, float* out_T, int32_t* out_n, int32_t* out_last,
+                        int32_t* out_idx, uint64_t* counters, hipStream_t s) {
+    if (o.tile == 8)
+        return launch<CPL, FT, 1, 32>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o, out_feat,
+                                      out_T, out_n, out_last, out_idx, counters, s);
+    return launch<CPL, FT, 4, 32>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o, out_feat,
+                                  out_T, out_n, out_last, out_idx, counters, s);
+}
+
+}  // namespace
+
+hipError_t fs_launch_render_forward(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges,
+                                    const void* feats, int C, int64_t n, const fs_camera* cams, int num_views,
+                                    int64_t total_tiles, const fs_opts& o, float* out_feat, float* out_T,
+                                    int32_t* out_n, int32_t* out_last, int32_t* out_idx, uint64_t* counters,
+                                    const FsWorkspace& ws, hipStream_t s) {
+    (void)ws;
+    if (total_tiles == 0) return hipSuccess;
+    const bool bf16 = o.feat_dtype == FS_FEAT_BF16;
+    if (C <= 64) {
+        return bf16 ? launch_waves<1, uint16_t>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o,
+                                                out_feat, out_T, out_n, out_last, out_idx, counters, s)
+                    : launch_waves<1, float>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o,
+                                             out_feat, out_T, out_n, out_last, out_idx, counters, s);
+    }
+    return bf16 ? launch_waves<2, uint16_t>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o,
+                                            out_feat, out_T, out_n, out_last, out_idx, counters, s)
+                : launch_waves<2, float>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o,
+                                         out_feat, out_T, out_n, out_last, out_idx, counters, s);
+}

@@ -1,0 +1,250 @@
+"""Python front end of the MI355X surfel feature rasterizer.
+
+PyTorch supplies device memory and the current HIP stream; every stage runs
+in the HIP library through the C ABI (see include/fastsegsim.h):
+
+    preprocess -> bin -> sort -> render_forward  (-> render_backward)
+
+The Rasterizer owns the per-frame buffers (records, key/value pairs, tile
+ranges, workspace) and grows the pair buffers when a frame needs more.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+ALPHA_MIN = 1.0 / 255.0
+ALPHA_MAX = 0.99
+T_STOP = 1e-4
+
+
+def _p(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _f32(t: torch.Tensor, shape, name: str) -> torch.Tensor:
+    if t.dtype != torch.float32 or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be a contiguous float32 tensor of shape {tuple(shape)}, got "
+                         f"{t.dtype} {tuple(t.shape)}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU")
+    return t
+
+
+@dataclass
+class Frame:
+    """Outputs (and intermediates) of one rendered frame."""
+    feat: torch.Tensor          # (total_pixels, C) float32
+    T: torch.Tensor             # (total_pixels,) float32
+    n: torch.Tensor             # (total_pixels,) int32
+    last: torch.Tensor | None   # (total_pixels,) int32
+    idx: torch.Tensor | None    # (total_pixels, K) int32
+    num_pairs: int
+    records: torch.Tensor
+    tiles_touched: torch.Tensor
+    keys: torch.Tensor          # sorted, first num_pairs valid
+    vals: torch.Tensor
+    ranges: torch.Tensor        # (total_tiles, 2)
+
+    def view_image(self, rast: "Rasterizer", v: int = 0, what: str = "feat") -> torch.Tensor:
+        cam = rast.cam_arr[v]
+        a = getattr(self, what)
+        sl = a[cam.pixel_offset: cam.pixel_offset + cam.width * cam.height]
+        return sl.reshape((cam.height, cam.width) + tuple(a.shape[1:]))
+
+
+class Rasterizer:
+    """Renders C-channel feature images of a surfel scene from one or more views."""
+
+    def __init__(self, cams, *, tile: int = 16, topk: int = 0, tile_mode: str = "precise",
+                 feat_dtype: str = "f32", alpha_min: float = ALPHA_MIN, alpha_max: float = ALPHA_MAX,
+                 t_stop: float = T_STOP, batch: int = 0, device: str | torch.device = "cuda",
+                 pair_capacity: int = 0):
+        self.lib = L.load()
+        self.device = torch.device(device)
+        self.cams = list(cams) if isinstance(cams, (list, tuple)) else [cams]
+        self.num_views = len(self.cams)
+        mode = {"precise": L.FS_TILES_PRECISE, "bbox": L.FS_TILES_BBOX}[tile_mode]
+        dt = {"f32": L.FS_FEAT_F32, "bf16": L.FS_FEAT_BF16}[feat_dtype]
+        self.feat_dtype = feat_dtype
+        self.opts = L.make_opts(tile, topk, mode, dt, alpha_min, alpha_max, t_stop, batch)
+        self.cam_arr, self.total_tiles, self.total_pixels = L.make_cameras(self.cams, tile)
+        raw = bytes(ctypes.string_at(ctypes.addressof(self.cam_arr), ctypes.sizeof(self.cam_arr)))
+        self.cams_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)
+        self.capacity = int(pair_capacity)
+        self._n = -1
+        self._bufs: dict[str, torch.Tensor] = {}
+
+    @property
+    def topk(self) -> int:
+        return int(self.opts.topk)
+
+    # -- buffers ------------------------------------------------------------
+    def _ensure(self, n: int, capacity: int):
+        if n != self._n:
+            V = self.num_views
+            self._bufs["records"] = torch.empty(V * n * L.FS_RECORD_BYTES, dtype=torch.uint8, device=self.device)
+            self._bufs["tiles"] = torch.empty(V * n, dtype=torch.int32, device=self.device)
+            self._bufs["num_pairs"] = torch.zeros(1, dtype=torch.int64, device=self.device)
+            self._bufs["ranges"] = torch.empty(self.total_tiles * 2, dtype=torch.int32, device=self.device)
+            self._n = n
+        if capacity > self.capacity or "keys" not in self._bufs:
+            self.capacity = max(capacity, self.capacity, 1024)
+            self._bufs["keys"] = torch.empty(self.capacity, dtype=torch.int64, device=self.device)
+            self._bufs["vals"] = torch.empty(self.capacity, dtype=torch.int32, device=self.device)
+        ws = self.lib.fs_workspace_bytes(n, self.num_views, self.total_tiles, self.capacity, ctypes.byref(self.opts))
+        if "ws" not in self._bufs or self._bufs["ws"].numel() < ws:
+            self._bufs["ws"] = torch.empty(max(ws, 256), dtype=torch.uint8, device=self.device)
+
+    # -- stages -------------------------------------------------------------
+    def preprocess(self, means, scales, quats, opacity):
+        n = means.shape[0]
+        self._ensure(n, self.capacity or max(4096, 2 * n * self.num_views))
+        b = self._bufs
+        L.check(self.lib.fs_preprocess(_p(means), _p(scales), _p(quats), _p(opacity), n, _p(self.cams_dev),
+                                       self.num_views, ctypes.byref(self.opts), _p(b["records"]), _p(b["tiles"]),
+                                       _stream(self.device)), "fs_preprocess")
+        return b["records"], b["tiles"]
+
+    def bin(self, means, scales, quats, opacity) -> int:
+        n = means.shape[0]
+        for _ in range(4):
+            b = self._bufs
+            P = ctypes.c_int64(0)
+            st = self.lib.fs_bin(_p(means), _p(scales), _p(quats), _p(opacity), n, _p(self.cams_dev), self.num_views,
+                                 ctypes.byref(self.opts), _p(b["tiles"]), _p(b["keys"]), _p(b["vals"]),
+                                 self.capacity, _p(b["num_pairs"]), ctypes.byref(P), _p(b["ws"]),
+                                 _stream(self.device))
+            if st == L.FS_ERR_CAPACITY:
+                self._ensure(n, int(P.value * 1.25) + 1024)
+                continue
+            L.check(st, "fs_bin")
+            return int(P.value)
+        raise L.FastSegSimError(L.FS_ERR_CAPACITY, "fs_bin")
+
+    def sort(self, num_pairs: int):
+        b = self._bufs
+        L.check(self.lib.fs_sort(_p(b["keys"]), _p(b["vals"]), self.capacity, _p(b["num_pairs"]), num_pairs,
+                                 self.total_tiles, _p(b["ranges"]), _p(b["ws"]), _stream(self.device)), "fs_sort")
+        return b["ranges"]
+
+    def render_forward(self, feats, *, out=None, want_last: bool = False, want_idx: bool = False,
+                       counters: torch.Tensor | None = None):
+        n, C = feats.shape
+        if feats.dtype != (torch.bfloat16 if self.feat_dtype == "bf16" else torch.float32) or not feats.is_contiguous():
+            raise ValueError(f"feats must be contiguous {self.feat_dtype}")
+        b = self._bufs
+        dev = self.device
+        if out is None:
+            out = {
+                "feat": torch.empty((self.total_pixels, C), dtype=torch.float32, device=dev),
+                "T": torch.empty(self.total_pixels, dtype=torch.float32, device=dev),
+                "n": torch.empty(self.total_pixels, dtype=torch.int32, device=dev),
+                "last": torch.empty(self.total_pixels, dtype=torch.int32, device=dev) if want_last else None,
+                "idx": (torch.empty((self.total_pixels, self.topk), dtype=torch.int32, device=dev)
+                        if want_idx and self.topk > 0 else None),
+            }
+        L.check(self.lib.fs_render_forward(_p(b["records"]), _p(b["vals"]), _p(b["ranges"]), _p(feats), C, n,
+                                           _p(self.cams_dev), self.num_views, self.total_tiles,
+                                           ctypes.byref(self.opts), _p(out["feat"]), _p(out["T"]), _p(out["n"]),
+                                           _p(out["last"]), _p(out["idx"]), _p(counters), _p(b["ws"]), _stream(dev)),
+                "fs_render_forward")
+        return out
+
+    def render(self, means, scales, quats, opacity, feats, *, want_last: bool = False,
+               want_idx: bool = False) -> Frame:
+        n = means.shape[0]
+        _f32(means, (n, 3), "means")
+        _f32(scales, (n, 2), "scales")
+        _f32(quats, (n, 4), "quats")
+        _f32(opacity, (n,), "opacity")
+        self.preprocess(means, scales, quats, opacity)
+        P = self.bin(means, scales, quats, opacity)
+        self.sort(P)
+        out = self.render_forward(feats, want_last=want_last, want_idx=want_idx)
+        b = self._bufs
+        return Frame(out["feat"], out["T"], out["n"], out["last"], out["idx"], P, b["records"], b["tiles"],
+                     b["keys"], b["vals"], b["ranges"].view(self.total_tiles, 2))
+
+    def render_nosync(self, means, scales, quats, opacity, feats, out: dict, counters=None, events=None) -> None:
+        """All four stages without any host synchronisation (the pair count
+        stays on the device; launches are sized by the pair capacity, which a
+        previous ``render`` call established).  Check ``pairs_fit()`` after."""
+        n = means.shape[0]
+        b = self._bufs
+        if n != self._n or "keys" not in b:
+            raise RuntimeError("render_nosync needs a prior render() with the same scene size")
+        dev = self.device
+        ev = events if events is not None else [None] * 5
+        if ev[0] is not None:
+            ev[0].record()
+        L.check(self.lib.fs_preprocess(_p(means), _p(scales), _p(quats), _p(opacity), n, _p(self.cams_dev),
+                                       self.num_views, ctypes.byref(self.opts), _p(b["records"]), _p(b["tiles"]),
+                                       _stream(dev)), "fs_preprocess")
+        if ev[1] is not None:
+            ev[1].record()
+        L.check(self.lib.fs_bin(_p(means), _p(scales), _p(quats), _p(opacity), n, _p(self.cams_dev), self.num_views,
+                                ctypes.byref(self.opts), _p(b["tiles"]), _p(b["keys"]), _p(b["vals"]), self.capacity,
+                                _p(b["num_pairs"]), None, _p(b["ws"]), _stream(dev)), "fs_bin")
+        if ev[2] is not None:
+            ev[2].record()
+        L.check(self.lib.fs_sort(_p(b["keys"]), _p(b["vals"]), self.capacity, _p(b["num_pairs"]), -1,
+                                 self.total_tiles, _p(b["ranges"]), _p(b["ws"]), _stream(dev)), "fs_sort")
+        if ev[3] is not None:
+            ev[3].record()
+        self.render_forward(feats, out=out, counters=counters)
+        if ev[4] is not None:
+            ev[4].record()
+
+    def pairs_fit(self) -> bool:
+        return int(self._bufs["num_pairs"].item()) <= self.capacity
+
+    def alloc_out(self, C: int, want_last: bool = False, want_idx: bool = False) -> dict:
+        dev = self.device
+        return {
+            "feat": torch.empty((self.total_pixels, C), dtype=torch.float32, device=dev),
+            "T": torch.empty(self.total_pixels, dtype=torch.float32, device=dev),
+            "n": torch.empty(self.total_pixels, dtype=torch.int32, device=dev),
+            "last": torch.empty(self.total_pixels, dtype=torch.int32, device=dev) if want_last else None,
+            "idx": (torch.empty((self.total_pixels, self.topk), dtype=torch.int32, device=dev)
+                    if want_idx and self.topk > 0 else None),
+        }
+
+    def render_backward(self, means, scales, quats, opacity, feats, frame: Frame, grad_feat: torch.Tensor):
+        """Gradients of sum(grad_feat * frame.feat); returns a dict of tensors."""
+        n, C = feats.shape
+        dev = self.device
+        b = self._bufs
+        g = {
+            "means": torch.zeros((n, 3), dtype=torch.float32, device=dev),
+            "scales": torch.zeros((n, 2), dtype=torch.float32, device=dev),
+            "quats": torch.zeros((n, 4), dtype=torch.float32, device=dev),
+            "opacity": torch.zeros(n, dtype=torch.float32, device=dev),
+            "feats": torch.zeros((n, C), dtype=torch.float32, device=dev),
+        }
+        grec = torch.empty(self.num_views * n * L.FS_GRAD_RECORD_FLOATS, dtype=torch.float32, device=dev)
+        gf = grad_feat.contiguous().float()
+        L.check(self.lib.fs_render_backward(_p(means), _p(scales), _p(quats), _p(opacity), _p(b["records"]),
+                                            _p(b["vals"]), _p(b["ranges"]), _p(feats), C, n, _p(self.cams_dev),
+                                            self.num_views, self.total_tiles, ctypes.byref(self.opts), _p(frame.T),
+                                            _p(frame.n), _p(frame.last), _p(gf), _p(grec), _p(g["means"]),
+                                            _p(g["scales"]), _p(g["quats"]), _p(g["opacity"]), _p(g["feats"]),
+                                            _p(b["ws"]), _stream(dev)), "fs_render_backward")
+        return g
+
+
+def scene_tensors(scene, device="cuda", feat_dtype: str = "f32"):
+    """Upload a scene (numpy arrays) as contiguous device tensors."""
+    t = lambda a: torch.from_numpy(a).to(device).contiguous()
+    feats = t(scene.feats)
+    if feat_dtype == "bf16":
+        feats = feats.to(torch.bfloat16).contiguous()
+    return t(scene.means), t(scene.scales), t(scene.quats), t(scene.opacity), feats

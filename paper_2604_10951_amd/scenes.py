@@ -95,6 +95,23 @@ def _unit_quats(rng: np.random.Generator, n: int) -> np.ndarray:
     return q.astype(np.float32)
 
 
+def _normal32_into(rng: np.random.Generator, out: np.ndarray, scale: float, rows: int = 16384) -> None:
+    """Fill a 2-D float32 array with N(0, scale^2) by the Box-Muller transform
+    of float32 uniforms, chunk by chunk (few large temporaries)."""
+    n, c = out.shape
+    for r0 in range(0, n, rows):
+        blk = out[r0:r0 + rows]
+        size = blk.size
+        half = (size + 1) // 2
+        u1 = rng.random(half, dtype=np.float32)
+        u2 = rng.random(half, dtype=np.float32)
+        rad = np.sqrt(np.float32(-2.0) * np.log1p(-u1)) * np.float32(scale)
+        ang = np.float32(2.0 * np.pi) * u2
+        flat = blk.reshape(-1)
+        flat[:half] = rad * np.cos(ang)
+        flat[half:] = (rad * np.sin(ang))[:size - half]
+
+
 def _log_uniform(rng: np.random.Generator, lo: float, hi: float, shape) -> np.ndarray:
     return np.exp(rng.uniform(np.log(lo), np.log(hi), size=shape)).astype(np.float32)
 
@@ -135,7 +152,7 @@ def clustered_scene(n: int, channels: int, *, seed: int = 0, box: tuple[float, f
     width at the near face).  Cluster centres are uniform in the box; each
     surfel picks a cluster uniformly and is placed at centre + N(0, sigma^2 I).
     Features are a scaled one-hot code of the cluster id plus small noise:
-    c_j = [j == cluster] * N(1, 0.1) + N(0, 0.05).
+    c_j = [j == cluster] * N(1, 0.1) + N(0, 0.05^2).
     """
     rng = np.random.default_rng(seed)
     a, b, c = box
@@ -147,12 +164,11 @@ def clustered_scene(n: int, channels: int, *, seed: int = 0, box: tuple[float, f
     scales = _log_uniform(rng, scale_range[0], scale_range[1], (n, 2))
     quats = _unit_quats(rng, n)
     opacity = _sigmoid(rng.normal(opacity_mu, opacity_sd, size=n)).astype(np.float32)
-    feats = np.zeros((n, channels), np.float32)
+    feats = np.empty((n, channels), np.float32)
+    _normal32_into(rng, feats, 0.05)
     hot = cluster % channels
-    feats[np.arange(n), hot] = rng.normal(1.0, 0.1, size=n)
-    feats += rng.normal(0.0, 0.05, size=(n, channels)).astype(np.float32)
-    return Scene(means, scales, quats, opacity, np.ascontiguousarray(feats.astype(np.float32)),
-                 cluster.astype(np.int32), centres.astype(np.float32))
+    feats[np.arange(n), hot] += (1.0 + 0.1 * rng.standard_normal(n)).astype(np.float32)
+    return Scene(means, scales, quats, opacity, feats, cluster.astype(np.int32), centres.astype(np.float32))
 
 
 def lookat_camera(eye, target, width: int, height: int, down=(0.0, 1.0, 0.0), focal: float | None = None) -> Camera:

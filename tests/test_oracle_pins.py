@@ -59,7 +59,8 @@ def test_fronto_parallel_splat_is_textbook_gaussian():
     ref = ((xs[None, :] - x0) / sx) ** 2 + ((ys[:, None] - y0) / sy) ** 2
     np.testing.assert_allclose(d2, ref, rtol=1e-12, atol=1e-12)
     # and the cutoff is the opacity-aware one: alpha >= 1/255 <=> d2 <= 2 ln(255 o)
-    assert proj.k2[0] == pytest.approx(2 * np.log(0.7 * 255), rel=1e-15)
+    assert proj.k2[0] == pytest.approx(2 * np.log(0.7 / oracle.ALPHA_MIN), rel=1e-15)
+    assert oracle.ALPHA_MIN == pytest.approx(1 / 255, rel=1e-7)
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
