@@ -196,7 +196,10 @@ fs_status fs_render_forward(const void* records, const uint32_t* vals, const uin
  * The blend's discrete choices (accepted surfels, stopping points, the Top-K
  * set, the alpha clamp) are held fixed, so only the selected surfels receive
  * gradient.  grad_records is caller scratch of num_views * n *
- * FS_GRAD_RECORD_FLOATS floats (zeroed by this call).
+ * FS_GRAD_RECORD_FLOATS floats (zeroed by this call).  Gradients are summed
+ * with float atomics, so their last bits depend on scheduling.  C <= 128
+ * (FS_ERR_UNSUPPORTED above).  The forward outputs out_T / out_last must come
+ * from fs_render_forward on the same records, vals and tile_ranges.
  */
 fs_status fs_render_backward(const float* means, const float* scales, const float* quats, const float* opacity,
                              const void* records, const uint32_t* vals, const uint32_t* tile_ranges,

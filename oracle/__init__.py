@@ -78,7 +78,8 @@ def load():
                                       _d, _d, _d, _i32, _i32, _i32, _i32]
     lib.fso_render_image.argtypes = [_i32, _u32, _d, _d, _d, _d, I64, I32, I32, I32, I32, D, D, D, I32, I32,
                                      _d, _d, _d, _i32, _i32, _i32, _i32]
-    lib.fso_render_grad.argtypes = [_d, _d, _d, _d, _d, I64, I32, _d, I32, D, D, D, I32, _d, _d, _d, _d, _d, _d]
+    lib.fso_render_grad.argtypes = [_d, _d, _d, _d, _d, I64, I32, _d, I32, D, D, D, I32, _d, _d, _d, _d, _d, _d,
+                                    _d, _d, _d, _d, _d]
     _lib = lib
     return lib
 
@@ -279,25 +280,29 @@ class Grads:
     quats: np.ndarray
     opacity: np.ndarray
     feats: np.ndarray
+    abs: "Grads | None" = None   # absolute-term sums (error scale), if requested
 
 
 def render_grad(means, scales, quats, opacity, feats, cam, g, *, K: int = 0, alpha_min: float = ALPHA_MIN,
-                alpha_max: float = ALPHA_MAX, t_stop: float = T_STOP, prefilter: bool = True) -> Grads:
+                alpha_max: float = ALPHA_MAX, t_stop: float = T_STOP, prefilter: bool = True,
+                with_abs: bool = False) -> Grads:
     """Gradient of sum(g * F) w.r.t. means, (activated) scales, raw quaternions,
-    (activated) opacity and features; g has shape (H, W, C)."""
+    (activated) opacity and features; g has shape (H, W, C).  With with_abs,
+    also the sums of absolute values of the terms of each gradient."""
     lib = load()
     means, scales, quats, opacity, feats = _f64(means), _f64(scales), _f64(quats), _f64(opacity), _f64(feats)
     n, C = feats.shape
     g = _f64(g).reshape(cam.height * cam.width, C)
-    gm, gs, gq = np.zeros((n, 3)), np.zeros((n, 2)), np.zeros((n, 4))
-    go, gf = np.zeros(n), np.zeros((n, C))
+    out = [np.zeros((n, 3)), np.zeros((n, 2)), np.zeros((n, 4)), np.zeros(n), np.zeros((n, C))]
+    ab = [np.zeros((n, 3)), np.zeros((n, 2)), np.zeros((n, 4)), np.zeros(n), np.zeros((n, C))] if with_abs else None
     ca = camera_array(cam)
+    aptr = [_ptr(a, _d) for a in ab] if with_abs else [None] * 5
     rc = lib.fso_render_grad(_ptr(means, _d), _ptr(scales, _d), _ptr(quats, _d), _ptr(opacity, _d), _ptr(feats, _d),
                              n, C, _ptr(ca, _d), int(prefilter), alpha_min, alpha_max, t_stop, K, _ptr(g, _d),
-                             _ptr(gm, _d), _ptr(gs, _d), _ptr(gq, _d), _ptr(go, _d), _ptr(gf, _d))
+                             *[_ptr(a, _d) for a in out], *aptr)
     if rc != 0:
         raise MemoryError("oracle render_grad failed")
-    return Grads(gm, gs, gq, go, gf)
+    return Grads(*out, abs=Grads(*ab) if with_abs else None)
 
 
 # ---------------------------------------------------------------------------

@@ -710,8 +710,15 @@ static void chain_to_params(const double p[3], const double s[2], const double q
 int fso_render_grad(const double* means, const double* scales, const double* quats, const double* opacity,
                     const double* feats, int64_t n, int C, const double* cam, int prefilter, double alpha_min,
                     double alpha_max, double t_stop, int K, const double* g, double* gmeans, double* gscales,
-                    double* gquats, double* gopac, double* gfeats)
+                    double* gquats, double* gopac, double* gfeats, double* amean, double* ascale, double* aquat,
+                    double* aopac, double* afeat)
 {
+    /* a* (optional, all or none): sums of the absolute values of the terms
+     * each gradient is made of -- per (pixel, contributor) for opacity and
+     * features; for centre, scales and quaternion |J| sum_p |dH_p|, with J
+     * the (linear) map from dL/dH to the parameters -- the scale against
+     * which the rounding error of a float32 gradient is judged. */
+    const int want_abs = amean != NULL;
     const int W = (int)cam[CW], Hh = (int)cam[CH];
     int32_t* valid = (int32_t*)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
     uint32_t* zkey = (uint32_t*)malloc(sizeof(uint32_t) * (n > 0 ? n : 1));
@@ -719,11 +726,16 @@ int fso_render_grad(const double* means, const double* scales, const double* qua
     double* H = (double*)malloc(sizeof(double) * 9 * (n > 0 ? n : 1));
     double* k2 = (double*)malloc(sizeof(double) * (n > 0 ? n : 1));
     double* dH = (double*)calloc((size_t)9 * (n > 0 ? n : 1), sizeof(double));
-    if (!valid || !zkey || !T || !H || !k2 || !dH) return -1;
+    double* dHa = want_abs ? (double*)calloc((size_t)9 * (n > 0 ? n : 1), sizeof(double)) : NULL;
+    if (!valid || !zkey || !T || !H || !k2 || !dH || (want_abs && !dHa)) return -1;
     fso_project(means, scales, quats, opacity, n, cam, alpha_min, valid, zkey, T, H, k2);
     for (int64_t i = 0; i < n; ++i) {
         gopac[i] = 0.0;
         for (int c = 0; c < C; ++c) gfeats[i * C + c] = 0.0;
+        if (want_abs) {
+            aopac[i] = 0.0;
+            for (int c = 0; c < C; ++c) afeat[i * C + c] = 0.0;
+        }
     }
     const int64_t npix = (int64_t)W * Hh;
     /* candidate lists, built as in fso_render_image */
@@ -806,11 +818,14 @@ int fso_render_grad(const double* means, const double* scales, const double* qua
         for (int j = nc - 1; j >= 0; --j) {
             const uint32_t i = who[j];
             for (int ch = 0; ch < C; ++ch) gfeats[(int64_t)i * C + ch] += wts[j] * gp[ch];
+            if (want_abs)
+                for (int ch = 0; ch < C; ++ch) afeat[(int64_t)i * C + ch] += wts[j] * fabs(gp[ch]);
             const double dalpha = Ts[j] * gc[j] - suffix / (1.0 - alphas[j]);
             suffix += wts[j] * gc[j];
             if (clamped[j]) continue;
             const double G = exp(-0.5 * d2s[j]);
             gopac[i] += G * dalpha;
+            if (want_abs) aopac[i] += fabs(G * dalpha);
             const double dG = opacity[i] * dalpha;
             const double dd2 = -0.5 * G * dG;
             const double* Hi = H + 9 * i;
@@ -822,7 +837,10 @@ int fso_render_grad(const double* means, const double* scales, const double* qua
             const double dh[3] = {du / h2, dv / h2, -(u * du + v * dv) / h2};
             const double xv[3] = {x, y, 1.0};
             for (int r = 0; r < 3; ++r)
-                for (int k = 0; k < 3; ++k) dH[9 * i + 3 * r + k] += dh[r] * xv[k];
+                for (int k = 0; k < 3; ++k) {
+                    dH[9 * i + 3 * r + k] += dh[r] * xv[k];
+                    if (want_abs) dHa[9 * i + 3 * r + k] += fabs(dh[r] * xv[k]);
+                }
         }
     }
     for (int64_t i = 0; i < n; ++i) {
@@ -832,7 +850,29 @@ int fso_render_grad(const double* means, const double* scales, const double* qua
         if (!valid[i]) continue;
         chain_to_params(means + 3 * i, scales + 2 * i, quats + 4 * i, cam, dH + 9 * i, gmeans + 3 * i,
                         gscales + 2 * i, gquats + 4 * i);
+        if (want_abs) {
+            for (int k = 0; k < 3; ++k) amean[3 * i + k] = 0.0;
+            ascale[2 * i] = ascale[2 * i + 1] = 0.0;
+            for (int k = 0; k < 4; ++k) aquat[4 * i + k] = 0.0;
+            for (int col = 0; col < 9; ++col) {   /* |J| (sum_p |dH_p|), one column of J at a time */
+                double e[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, jm[3], js[2], jq[4];
+                e[col] = 1.0;
+                chain_to_params(means + 3 * i, scales + 2 * i, quats + 4 * i, cam, e, jm, js, jq);
+                const double y = dHa[9 * i + col];
+                for (int k = 0; k < 3; ++k) amean[3 * i + k] += fabs(jm[k]) * y;
+                for (int k = 0; k < 2; ++k) ascale[2 * i + k] += fabs(js[k]) * y;
+                for (int k = 0; k < 4; ++k) aquat[4 * i + k] += fabs(jq[k]) * y;
+            }
+        }
     }
+    if (want_abs)
+        for (int64_t i = 0; i < n; ++i)
+            if (!valid[i]) {
+                for (int k = 0; k < 3; ++k) amean[3 * i + k] = 0.0;
+                ascale[2 * i] = ascale[2 * i + 1] = 0.0;
+                for (int k = 0; k < 4; ++k) aquat[4 * i + k] = 0.0;
+            }
+    free(dHa);
     free(valid);
     free(zkey);
     free(T);

@@ -183,7 +183,7 @@ fs_status fs_render_backward(const float* means, const float* scales, const floa
         !out_last || !grad_feat || !grad_records || !grad_means || !grad_scales || !grad_quats || !grad_opacity ||
         !grad_feats)
         return FS_ERR_ARG;
-    if (C > 1024) return FS_ERR_UNSUPPORTED;
+    if (C > 128) return FS_ERR_UNSUPPORTED;   // one channel chunk per block in the backward
     FsWorkspace ws;
     memset(&ws, 0, sizeof(ws));
     (void)workspace;

@@ -1,10 +1,391 @@
-// render_bwd.hip -- backward of the blend (written next).
+// render_bwd.hip -- gradients of L = sum_p g_p . F_p through the blend
+// (Sec. 3.1 Eq. 2, Top-K of Sec. 3.4), the ray-splat intersection and the
+// projection (Sec. 3.1 Eq. 1, Sec. 3.2 T) back to the surfel parameters.
+//
+// With contributors m of a pixel in depth order, w_m = alpha_m T_m:
+//   dL/dc_m     = w_m g
+//   dL/dalpha_m = T_m (g . c_m) - S_m / (1 - alpha_m),  S_m = sum_{l > m} w_l (g . c_l)
+//   alpha = o exp(-d2 / 2) unless clamped at alpha_max (then no gradient)
+//   d2 = u^2 + v^2, (u, v) = (h0 / h2, h1 / h2), h = L (1, dx, dy)
+// where L is the anchored, normalised 3x3 coefficient matrix of the record.
+// The blend's discrete choices are those of the forward pass: the same
+// double-precision response decides acceptance, and entries after the
+// pixel's last blended position are skipped.
+//
+// Kernel 1 (per 8x8 block, one wave): the tile list is walked back to front
+// in batches.  Lanes = pixels recover T by division from the forward's final
+// transmittance and form the weights; lanes = channels form g . c_m (a wave
+// reduction per contribution) and accumulate w g into per-entry LDS rows;
+// lanes = pixels then run the scalar chain to dL/dL (9) and dL/do, reduced
+// over the wave per entry.  Per-entry results go to global memory with
+// atomics (float, so the sum order, hence the last bits, can vary).
+// Kernel 2 (per surfel): dL/dL -> dL/dadj(T) -> dL/dT -> centre, scales,
+// quaternion, summed over views, in double precision.
 #include "fs_internal.h"
 
-hipError_t fs_launch_render_backward(const float*, const float*, const float*, const float*, const FsRecord*,
-                                     const uint32_t*, const uint32_t*, const void*, int, int64_t, const fs_camera*,
-                                     int, int64_t, const fs_opts&, const float*, const int32_t*, const int32_t*,
-                                     const float*, float*, float*, float*, float*, float*, float*,
-                                     const FsWorkspace&, hipStream_t) {
-    return hipErrorNotSupported;
+namespace {
+
+constexpr int BG = 32;
+constexpr int kGradFloats = FS_GRAD_RECORD_FLOATS;   // 9 (dL/dL) + 1 (dL/do) + 2 pad
+
+FS_DEV float bf16_to_f32b(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+template <typename FT>
+FS_DEV float to_f32(FT x);
+template <>
+FS_DEV float to_f32<float>(float x) { return x; }
+template <>
+FS_DEV float to_f32<uint16_t>(uint16_t x) { return bf16_to_f32b(x); }
+
+FS_DEV float wave_sum(float x) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+__global__ void zero_f32_kernel(float* p, int64_t count) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0.f;
+}
+
+template <int CPL, typename FT>
+__global__ void __launch_bounds__(64)
+render_bwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restrict__ vals,
+                  const uint32_t* __restrict__ ranges, const FT* __restrict__ feats, int C, int64_t n,
+                  int64_t num_records, const fs_camera* __restrict__ cams, int num_views, int S, fs_opts o,
+                  const float* __restrict__ out_T, const int32_t* __restrict__ out_last,
+                  const float* __restrict__ grad_feat, float* __restrict__ grad_records,
+                  float* __restrict__ grad_feats) {
+    constexpr int kChunk = 64 * CPL;
+    __shared__ FsRecord s_rec[BG];
+    __shared__ uint32_t s_recid[BG];
+    __shared__ float s_feat[BG][kChunk];
+    __shared__ float s_dfeat[BG][kChunk];
+    __shared__ float s_w[BG][64];
+    __shared__ float s_D[BG][64];
+    __shared__ float s_grec[BG][kGradFloats];
+
+    const int lane = threadIdx.x;
+    // block position (8x8 pixels inside a binning tile)
+    const int sb = S / 8;
+    const int64_t b = blockIdx.x;
+    const int64_t tile = b / (sb * sb);
+    const int sub = (int)(b % (sb * sb));
+    const int v = fs_view_of_tile(cams, num_views, tile);
+    const fs_camera& cam = cams[v];
+    const int tiles_x = (cam.width + S - 1) / S;
+    const int64_t local = tile - cam.tile_offset;
+    const int wx0 = (int)(local % tiles_x) * S + (sub % sb) * 8;
+    const int wy0 = (int)(local / tiles_x) * S + (sub / sb) * 8;
+    if (wx0 >= cam.width || wy0 >= cam.height) return;
+    const int px = wx0 + (lane & 7), py = wy0 + (lane >> 3);
+    const bool inside = px < cam.width && py < cam.height;
+    const int64_t pix = cam.pixel_offset + (int64_t)py * cam.width + px;
+    const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    const int last = inside ? out_last[pix] : -1;
+    // walk back from the block's last blended entry
+    int maxlast = last;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) maxlast = max(maxlast, __shfl_xor(maxlast, d, 64));
+    if (maxlast < (int)start) return;   // nothing was blended in this block
+    double T = inside ? (double)out_T[pix] : 1.0;
+    float suffix = 0.f;                 // S: sum over later contributors of w (g . c)
+
+    // upstream gradient of the block's pixels, lanes = channels
+    float G[64][CPL];
+#pragma unroll
+    for (int p = 0; p < 64; ++p) {
+        const int qx = wx0 + (p & 7), qy = wy0 + (p >> 3);
+        const bool in = qx < cam.width && qy < cam.height;
+        const int64_t q = cam.pixel_offset + (int64_t)qy * cam.width + qx;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int ch = lane * CPL + c;
+            G[p][c] = (in && ch < C) ? grad_feat[q * C + ch] : 0.f;
+        }
+    }
+
+    const uint32_t top = (uint32_t)maxlast + 1u;
+    const uint32_t nbatch = (top - start + BG - 1) / BG;
+    for (uint32_t bi = nbatch; bi-- > 0;) {
+        const uint32_t b0 = start + bi * BG;
+        const int nb = (int)(top - b0 < (uint32_t)BG ? top - b0 : (uint32_t)BG);
+        // 1. stage records
+        constexpr int kQ = FS_RECORD_BYTES / 16;
+        for (int t = lane; t < nb * kQ; t += 64) {
+            const int e = t / kQ, q = t - e * kQ;
+            uint32_t rid = vals[b0 + e];
+            float4 v4 = make_float4(0.f, 0.f, 0.f, 0.f);
+            if ((int64_t)rid < num_records) {
+                v4 = reinterpret_cast<const float4*>(records + rid)[q];
+            } else {
+                rid = 0u;
+                if (q == 4) v4.w = __int_as_float((int)0xbff00000);
+                if (q == 5) v4.z = __int_as_float(1);
+            }
+            reinterpret_cast<float4*>(&s_rec[e])[q] = v4;
+            if (q == 0) s_recid[e] = rid;
+        }
+        for (int t = lane; t < BG * kGradFloats; t += 64) (&s_grec[0][0])[t] = 0.f;
+        for (int t = lane; t < BG * kChunk; t += 64) (&s_dfeat[0][0])[t] = 0.f;
+        __syncthreads();
+        // 2. weights, back to front (lanes = pixels)
+        uint32_t mask = 0u;
+        for (int e = nb - 1; e >= 0; --e) {
+            const FsRecord& r = s_rec[e];
+            if (r.x1 < wx0 || r.x0 > wx0 + 7 || r.y1 < wy0 || r.y0 > wy0 + 7) continue;
+            if ((int)(b0 + e) > last) continue;
+            const FsResp rs = fs_response(r, (double)(px - r.ax), (double)(py - r.ay));
+            if (rs.d2 <= r.k2) {
+                const float Gs = __builtin_amdgcn_exp2f(-0.72134752044448170f * (float)rs.d2);
+                const float alpha = fminf(o.alpha_max, r.o * Gs);
+                T = T / (1.0 - (double)alpha);
+                s_w[e][lane] = (float)((double)alpha * T);
+                mask |= 1u << e;
+            }
+        }
+        const uint32_t used = [&] {
+            uint32_t x = mask;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) x |= __shfl_xor(x, d, 64);
+            return x;
+        }();
+        const uint64_t active_px = __ballot(mask != 0u);
+        // 3. feature rows of used entries
+        for (int t = lane; t < BG * kChunk; t += 64) {
+            const int e = t / kChunk, c = t - e * kChunk;
+            // channels >= C are zeroed: the wave-wide dot products read every lane
+            if ((used >> e) & 1u) s_feat[e][c] = c < C ? to_f32(feats[fs_surfel_of(s_recid[e], n) * C + c]) : 0.f;
+        }
+        __syncthreads();
+        // 4. lanes = channels: D = g . c per contribution, dL/dc += w g per entry
+#pragma unroll
+        for (int p = 0; p < 64; ++p) {
+            if ((active_px >> p) & 1ull) {
+                uint32_t m = __builtin_amdgcn_readlane(mask, p);
+                while (m) {
+                    const int e = __builtin_ctz(m);
+                    m &= m - 1u;
+                    float part = 0.f;
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) part = fmaf(G[p][c], s_feat[e][lane * CPL + c], part);
+                    const float D = wave_sum(part);
+                    if (lane == 0) s_D[e][p] = D;
+                    const float w = s_w[e][p];
+#pragma unroll
+                    for (int c = 0; c < CPL; ++c) s_dfeat[e][lane * CPL + c] += w * G[p][c];
+                }
+            }
+        }
+        __syncthreads();
+        // 5. lanes = pixels: scalar chain back to front
+        for (int e = nb - 1; e >= 0; --e) {
+            if (!((used >> e) & 1u)) continue;
+            const bool mine = (mask >> e) & 1u;
+            float g[10];
+#pragma unroll
+            for (int k = 0; k < 10; ++k) g[k] = 0.f;
+            if (mine) {
+                const FsRecord& r = s_rec[e];
+                const double ddx = (double)(px - r.ax), ddy = (double)(py - r.ay);
+                const FsResp rs = fs_response(r, ddx, ddy);
+                const float Gs = __builtin_amdgcn_exp2f(-0.72134752044448170f * (float)rs.d2);
+                const float ag = r.o * Gs;
+                const bool clamped = ag > o.alpha_max;
+                const float alpha = clamped ? o.alpha_max : ag;
+                const float w = s_w[e][lane];
+                const float Tm = w / alpha;
+                const float D = s_D[e][lane];
+                const float dalpha = Tm * D - suffix / (1.f - alpha);
+                suffix = fmaf(w, D, suffix);
+                if (!clamped) {
+                    g[9] = Gs * dalpha;                        // dL/do
+                    const float dG = r.o * dalpha;
+                    const float dd2 = -0.5f * Gs * dG;
+                    const float u = (float)rs.u, vv = (float)rs.v, rh = (float)rs.rh;
+                    const float du = 2.f * u * dd2, dv = 2.f * vv * dd2;
+                    const float dh0 = du * rh, dh1 = dv * rh, dh2 = -(u * du + vv * dv) * rh;
+                    const float fx = (float)ddx, fy = (float)ddy;
+                    g[0] = dh0; g[1] = dh0 * fx; g[2] = dh0 * fy;
+                    g[3] = dh1; g[4] = dh1 * fx; g[5] = dh1 * fy;
+                    g[6] = dh2; g[7] = dh2 * fx; g[8] = dh2 * fy;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 10; ++k) {
+                const float sum = wave_sum(g[k]);
+                if (lane == 0) s_grec[e][k] = sum;
+            }
+        }
+        __syncthreads();
+        // 6. flush per-entry gradients
+        for (int t = lane; t < BG * kGradFloats; t += 64) {
+            const int e = t / kGradFloats, k = t - e * kGradFloats;
+            if (((used >> e) & 1u) && k < 10) atomicAdd(&grad_records[(int64_t)s_recid[e] * kGradFloats + k], s_grec[e][k]);
+        }
+        for (int t = lane; t < BG * kChunk; t += 64) {
+            const int e = t / kChunk, c = t - e * kChunk;
+            if (((used >> e) & 1u) && c < C)
+                atomicAdd(&grad_feats[fs_surfel_of(s_recid[e], n) * C + c], s_dfeat[e][c]);
+        }
+        __syncthreads();
+    }
+}
+
+// dL/dL (anchored, normalised record coefficients; columns: constant, dx, dy)
+// back to the surfel parameters.  L = adj(T) A / s with A mapping (1, dx, dy)
+// to (x, y, 1) = (xa + dx, ya + dy, 1); since (u, v) does not change when L is
+// scaled, the dependence of s on T contributes nothing and dL/dadj = dL/dL A^T / s.
+__global__ void __launch_bounds__(256)
+preprocess_bwd_kernel(const float* __restrict__ means, const float* __restrict__ scales,
+                      const float* __restrict__ quats, const float* __restrict__ opacity, int64_t n,
+                      const fs_camera* __restrict__ cams, int num_views, fs_opts o,
+                      const float* __restrict__ grad_records, float* __restrict__ gm, float* __restrict__ gs,
+                      float* __restrict__ gq, float* __restrict__ go) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double am[3] = {0, 0, 0}, as[2] = {0, 0}, aq[4] = {0, 0, 0, 0}, ao = 0.0;
+    for (int v = 0; v < num_views; ++v) {
+        const float* gr = grad_records + ((int64_t)v * n + i) * kGradFloats;
+        double dl[9];
+        bool any = false;
+        for (int k = 0; k < 9; ++k) {
+            dl[k] = gr[k];
+            any = any || dl[k] != 0.0;
+        }
+        ao += gr[9];
+        if (!any) continue;
+        const fs_camera& cam = cams[v];
+        FsGeo g;
+        if (!fs_project(means + 3 * i, scales + 2 * i, quats + 4 * i, opacity[i], cam, (double)o.alpha_min, g))
+            continue;
+        FsFootprint fp;
+        fs_footprint(g, cam.width, cam.height, fp);
+        const double mx = g.T[2] / g.T[8], my = g.T[5] / g.T[8];
+        const double s = (g.H[6] * mx + g.H[7] * my) + g.H[8];
+        const double xa = fp.q.ax + 0.5, ya = fp.q.ay + 0.5;
+        // dL/dH = dL/dL A^T / s ; A = [[xa,1,0],[ya,0,1],[1,0,0]]  (rows of H act on (x, y, 1))
+        double dH[9];
+        for (int r = 0; r < 3; ++r) {
+            const double l0 = dl[3 * r], l1 = dl[3 * r + 1], l2 = dl[3 * r + 2];
+            dH[3 * r + 0] = (l0 * xa + l1) / s;   // column x
+            dH[3 * r + 1] = (l0 * ya + l2) / s;   // column y
+            dH[3 * r + 2] = l0 / s;               // column 1
+        }
+        // H columns: T2 x Tw, Tw x T1, T1 x T2 ; for c = a x b: dL/da = b x g, dL/db = g x a
+        const double* T1 = g.T;
+        const double* T2 = g.T + 3;
+        const double* Tw = g.T + 6;
+        double gx[3], gy[3], g1[3];
+        for (int r = 0; r < 3; ++r) {
+            gx[r] = dH[3 * r];
+            gy[r] = dH[3 * r + 1];
+            g1[r] = dH[3 * r + 2];
+        }
+        double dT1[3], dT2[3], dTw[3], t0[3], t1[3];
+        fs_cross(Tw, gx, t0);          // d(T2 x Tw)/dT2
+        fs_cross(T1, g1, t1);          // d(T1 x T2)/dT2 = g1 x T1
+        for (int k = 0; k < 3; ++k) dT2[k] = t0[k] - t1[k];
+        fs_cross(gx, T2, t0);          // d(T2 x Tw)/dTw
+        fs_cross(T1, gy, t1);          // d(Tw x T1)/dTw
+        for (int k = 0; k < 3; ++k) dTw[k] = t0[k] + t1[k];
+        fs_cross(gy, Tw, t0);          // d(Tw x T1)/dT1
+        fs_cross(T2, g1, t1);          // d(T1 x T2)/dT1
+        for (int k = 0; k < 3; ++k) dT1[k] = t0[k] + t1[k];
+        // T = K [U | V | pc]: rows T1 = fx M0 + cx M2, T2 = fy M1 + cy M2, Tw = M2
+        double dM0[3], dM1[3], dM2[3];
+        for (int c = 0; c < 3; ++c) {
+            dM0[c] = (double)cam.fx * dT1[c];
+            dM1[c] = (double)cam.fy * dT2[c];
+            dM2[c] = (double)cam.cx * dT1[c] + (double)cam.cy * dT2[c] + dTw[c];
+        }
+        const double dU[3] = {dM0[0], dM1[0], dM2[0]};
+        const double dV[3] = {dM0[1], dM1[1], dM2[1]};
+        const double dpc[3] = {dM0[2], dM1[2], dM2[2]};
+        FsFrame fr;
+        fs_frame(means + 3 * i, scales + 2 * i, quats + 4 * i, cam, fr);
+        double Rtu[3], Rtv[3], dtu[3], dtv[3];
+        for (int r = 0; r < 3; ++r) {
+            const double R0 = cam.R[3 * r], R1 = cam.R[3 * r + 1], R2 = cam.R[3 * r + 2];
+            Rtu[r] = (R0 * fr.tu[0] + R1 * fr.tu[1]) + R2 * fr.tu[2];
+            Rtv[r] = (R0 * fr.tv[0] + R1 * fr.tv[1]) + R2 * fr.tv[2];
+        }
+        const double s0 = scales[2 * i], s1 = scales[2 * i + 1];
+        for (int k = 0; k < 3; ++k) {
+            const double Rk0 = cam.R[k], Rk1 = cam.R[3 + k], Rk2 = cam.R[6 + k];   // column k of R
+            am[k] += (Rk0 * dpc[0] + Rk1 * dpc[1]) + Rk2 * dpc[2];
+            dtu[k] = s0 * ((Rk0 * dU[0] + Rk1 * dU[1]) + Rk2 * dU[2]);
+            dtv[k] = s1 * ((Rk0 * dV[0] + Rk1 * dV[1]) + Rk2 * dV[2]);
+        }
+        as[0] += fs_dot(Rtu, dU);
+        as[1] += fs_dot(Rtv, dV);
+        // quaternion: t_u = (1 - f a1, f a2, f a3), t_v = (f b1, 1 - f b2, f b3), f = 2 / |q|^2
+        const double w = quats[4 * i], x = quats[4 * i + 1], y = quats[4 * i + 2], z = quats[4 * i + 3];
+        const double f = fr.f;
+        const double a1 = y * y + z * z, a2 = x * y + w * z, a3 = x * z - w * y;
+        const double b1 = x * y - w * z, b2 = x * x + z * z, b3 = y * z + w * x;
+        const double sf = -dtu[0] * a1 + dtu[1] * a2 + dtu[2] * a3 + dtv[0] * b1 - dtv[1] * b2 + dtv[2] * b3;
+        const double q[4] = {w, x, y, z};
+        const double da1[4] = {0, 0, 2 * y, 2 * z}, da2[4] = {z, y, x, w}, da3[4] = {-y, z, -w, x};
+        const double db1[4] = {-z, y, x, -w}, db2[4] = {0, 2 * x, 0, 2 * z}, db3[4] = {x, w, z, y};
+        for (int k = 0; k < 4; ++k) {
+            const double inner = -dtu[0] * da1[k] + dtu[1] * da2[k] + dtu[2] * da3[k] + dtv[0] * db1[k] -
+                                 dtv[1] * db2[k] + dtv[2] * db3[k];
+            aq[k] += -f * f * q[k] * sf + f * inner;
+        }
+    }
+    for (int k = 0; k < 3; ++k) gm[3 * i + k] += (float)am[k];
+    gs[2 * i] += (float)as[0];
+    gs[2 * i + 1] += (float)as[1];
+    for (int k = 0; k < 4; ++k) gq[4 * i + k] += (float)aq[k];
+    go[i] += (float)ao;
+}
+
+template <int CPL, typename FT>
+hipError_t launch_bwd(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges, const void* feats,
+                      int C, int64_t n, const fs_camera* cams, int num_views, int64_t total_tiles, const fs_opts& o,
+                      const float* out_T, const int32_t* out_last, const float* grad_feat, float* grad_records,
+                      float* grad_feats, hipStream_t s) {
+    const int sb = o.tile / 8;
+    const int64_t blocks = total_tiles * sb * sb;
+    hipLaunchKernelGGL((render_bwd_kernel<CPL, FT>), dim3((unsigned)blocks), dim3(64), 0, s, records, vals, ranges,
+                       static_cast<const FT*>(feats), C, n, n * num_views, cams, num_views, o.tile, o, out_T,
+                       out_last, grad_feat, grad_records, grad_feats);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t fs_launch_render_backward(const float* means, const float* scales, const float* quats,
+                                     const float* opacity, const FsRecord* records, const uint32_t* vals,
+                                     const uint32_t* ranges, const void* feats, int C, int64_t n,
+                                     const fs_camera* cams, int num_views, int64_t total_tiles, const fs_opts& o,
+                                     const float* out_T, const int32_t* out_n, const int32_t* out_last,
+                                     const float* grad_feat, float* grad_records, float* grad_means,
+                                     float* grad_scales, float* grad_quats, float* grad_opacity, float* grad_feats,
+                                     const FsWorkspace& ws, hipStream_t s) {
+    (void)out_n;
+    (void)ws;
+    const int64_t nrec = n * num_views * kGradFloats;
+    {
+        unsigned blocks = (unsigned)((nrec + 255) / 256);
+        blocks = blocks < 1 ? 1 : (blocks > 8192 ? 8192 : blocks);
+        hipLaunchKernelGGL(zero_f32_kernel, dim3(blocks), dim3(256), 0, s, grad_records, nrec);
+    }
+    hipError_t e;
+    const bool bf16 = o.feat_dtype == FS_FEAT_BF16;
+    if (C <= 64)
+        e = bf16 ? launch_bwd<1, uint16_t>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o, out_T,
+                                           out_last, grad_feat, grad_records, grad_feats, s)
+                 : launch_bwd<1, float>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o, out_T,
+                                        out_last, grad_feat, grad_records, grad_feats, s);
+    else
+        e = bf16 ? launch_bwd<2, uint16_t>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o, out_T,
+                                           out_last, grad_feat, grad_records, grad_feats, s)
+                 : launch_bwd<2, float>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o, out_T,
+                                        out_last, grad_feat, grad_records, grad_feats, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(preprocess_bwd_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, means, scales,
+                       quats, opacity, n, cams, num_views, o, grad_records, grad_means, grad_scales, grad_quats,
+                       grad_opacity);
+    return hipGetLastError();
 }

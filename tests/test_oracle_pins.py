@@ -367,3 +367,17 @@ def test_gradient_matches_finite_differences(K):
         assert abs(a - f) <= 1e-4 * abs(a) + 1e-6 * scale + 1e-9, (grp, idx, a, f)
         valid += 1
     assert valid >= 0.6 * len(coords)
+
+
+def test_gradient_absolute_term_sums_bound_the_gradient():
+    sc, cam = _fd_scene()
+    rng = np.random.default_rng(4)
+    g = rng.standard_normal((cam.height, cam.width, sc.channels))
+    gr = oracle.render_grad(sc.means, sc.scales, sc.quats, sc.opacity, sc.feats, cam, g, K=3, with_abs=True)
+    for name in ("means", "scales", "quats", "opacity", "feats"):
+        a, s = getattr(gr, name), getattr(gr.abs, name)
+        assert np.all(s >= np.abs(a) * (1 - 1e-12) - 1e-15), name
+    # features: the terms are w_p g_p, so the sum of |terms| is sum_p w_p |g_p| -- the gradient
+    # of the same blend with |g| as upstream gradient
+    ga = oracle.render_grad(sc.means, sc.scales, sc.quats, sc.opacity, sc.feats, cam, np.abs(g), K=3)
+    np.testing.assert_allclose(gr.abs.feats, ga.feats, rtol=1e-12, atol=1e-15)
