@@ -69,6 +69,141 @@ def render_bytes(P, counters, H, W, C, feat_bytes=4):
     return P * (4 + 96) + counters["rows"] * C * feat_bytes + H * W * (4 * C + 8)
 
 
+def _time_frames(rast, tens, steps, warmup):
+    out = rast.alloc_out(tens[4].shape[1])
+    for _ in range(warmup):
+        rast.render_nosync(*tens, out)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        rast.render_nosync(*tens, out)
+    b.record()
+    torch.cuda.synchronize()
+    if not rast.pairs_fit():
+        raise RuntimeError("pair capacity exceeded")
+    return a.elapsed_time(b) / steps
+
+
+def _plain(cams, tens, dev, steps, warmup, topk=0, tile=8):
+    """Plain FP32 full blend (the comparison point of every form)."""
+    rast = raster.Rasterizer(cams, tile=tile, topk=topk, device=dev)
+    rast.render(*tens)
+    ms = _time_frames(rast, tens, steps, warmup)
+    del rast
+    torch.cuda.empty_cache()
+    return ms
+
+
+def form_bf16(dev, steps, warmup):
+    """1M surfels, 1280x720, C = 256, K = 16: bfloat16 against float32 storage."""
+    scene, cam = scenes.large_scene(256), scenes.centred_camera(1280, 720)
+    res = {"workload": "1M surfels, 1280x720, C=256, Top-K K=16, 8x8 tiles"}
+    t32 = raster.scene_tensors(scene, dev)
+    res["plain_f32_full_ms"] = _plain(cam, t32, dev, steps, warmup)
+    res["f32_topk_ms"] = _plain(cam, t32, dev, steps, warmup, topk=16)
+    t16 = raster.scene_tensors(scene, dev, "bf16")
+    del t32
+    torch.cuda.empty_cache()
+    rast = raster.Rasterizer(cam, tile=8, topk=16, feat_dtype="bf16", device=dev)
+    rast.render(*t16)
+    res["bf16_topk_ms"] = _time_frames(rast, t16, steps, warmup)
+    res["bf16_vs_plain_f32_full"] = res["plain_f32_full_ms"] / res["bf16_topk_ms"]
+    res["bf16_vs_f32_topk"] = res["f32_topk_ms"] / res["bf16_topk_ms"]
+    return res
+
+
+def form_batched(scene_tens, dev, steps, warmup):
+    """1M surfels, 16 look-at views of uneven resolution, C = 128, K = 8: one
+    hipGraph replay of the batched frame (persistent longest-first render)
+    against the 16 views rendered one after the other."""
+    cams = scenes.random_lookat_views(16, seed=1)
+    res = {"workload": "1M surfels, 16 views " + ",".join(f"{c.width}x{c.height}" for c in cams) +
+                       ", C=128, Top-K K=8, 8x8 tiles",
+           "pixels": int(sum(c.width * c.height for c in cams))}
+    rast = raster.Rasterizer(cams, tile=8, topk=8, schedule="persistent", device=dev)
+    graph = raster.FrameGraph(rast, scene_tens)
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        graph.replay()
+    b.record()
+    torch.cuda.synchronize()
+    assert graph.pairs_fit()
+    res["graph_batched_ms"] = a.elapsed_time(b) / steps
+    del graph, rast
+    torch.cuda.empty_cache()
+    singles = [raster.Rasterizer(c, tile=8, topk=0, device=dev) for c in cams]
+    outs = []
+    for r in singles:
+        r.render(*scene_tens)
+        outs.append(r.alloc_out(128))
+    for _ in range(warmup):
+        for r, o in zip(singles, outs):
+            r.render_nosync(*scene_tens, o)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps):
+        for r, o in zip(singles, outs):
+            r.render_nosync(*scene_tens, o)
+    b.record()
+    torch.cuda.synchronize()
+    res["plain_per_view_f32_full_ms"] = a.elapsed_time(b) / steps
+    res["batched_vs_plain"] = res["plain_per_view_f32_full_ms"] / res["graph_batched_ms"]
+    del singles, outs
+    torch.cuda.empty_cache()
+    return res
+
+
+def form_backward(dev, steps, warmup):
+    """200k surfels, 640x480, C = 128, K = 8: the hand-written backward against
+    the plain FP32 full-blend forward of the same scene."""
+    scene, cam = scenes.backward_scene()
+    tens = raster.scene_tensors(scene, dev)
+    res = {"workload": "200k surfels, 640x480, C=128, Top-K K=8, 8x8 tiles, upstream grad N(0,1)"}
+    res["plain_f32_full_ms"] = _plain(cam, tens, dev, steps, warmup)
+    rast = raster.Rasterizer(cam, tile=8, topk=8, device=dev)
+    fr = rast.render(*tens, want_last=True)
+    g = torch.from_numpy(scenes.upstream_grad(cam.height, cam.width, 128).reshape(-1, 128)).to(dev)
+    for _ in range(warmup):
+        rast.render_backward(*tens, fr, g)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        rast.render_backward(*tens, fr, g)
+    b.record()
+    torch.cuda.synchronize()
+    res["backward_ms"] = a.elapsed_time(b) / steps
+    res["backward_vs_plain_forward"] = res["plain_f32_full_ms"] / res["backward_ms"]
+    return res
+
+
+def measured_traffic():
+    """HBM bytes per Top-K render launch from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs, if the render sources are unchanged since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "render_fwd_topk_headline_traffic.json")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for p in rec["sources"]:
+            h.update(open(os.path.join(ROOT, p), "rb").read())
+        return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def frame_bytes(n, P, counters, H, W, C, feat_bytes=4):
+    """Algorithmic bytes of a whole frame: parameters read (40 B/surfel),
+    records written (96 B/surfel), pairs emitted, sorted once and read by the
+    render (12 + 24 + 100 B/pair), used feature rows, and the outputs."""
+    return 40 * n + 96 * n + (12 + 24 + 100) * P + counters["rows"] * C * feat_bytes + H * W * (4 * C + 8)
+
+
 def cpu_baseline(scene, cam):
     import oracle
     t0 = time.perf_counter()
@@ -92,12 +227,22 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tile", type=int, default=TILE)
+    ap.add_argument("--no-forms", action="store_true", help="skip the BF16 / batched / backward forms")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy a MIB-sized device buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is a design "
                                    "(views or screen regions per GPU), not measured here"}))
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"[bench] generating scene (seed {args.seed})", file=sys.stderr, flush=True)
     scene, cam = scenes.headline(seed=args.seed, channels=C)
     tens = raster.scene_tensors(scene, dev)
@@ -144,10 +289,23 @@ def main():
         "pairs": top["P"],
         "render_counters": {"topk": top["counters"], "full": full["counters"]},
         "roofline": {"kernel": "render_fwd_kernel (Top-K)", "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if args.tile == TILE else None,
                      "algorithmic_bytes": top["render_bytes"], "avg_launch_ms": top["render_ms"]},
-        "frame_hbm_frac": None,
+        "frame_hbm_frac": frame_bytes(scene.n, top["P"], top["counters"], H, W, C) / (top["ms"] * 1e-3) / 1e9
+                          / HBM_PEAK_GBS,
     }
+    if not args.no_forms:
+        fs, fw = 10, 2
+        print("[bench] form: batched views", file=sys.stderr, flush=True)
+        forms = {"batched": form_batched(tens, dev, fs, fw)}
+        del tens
+        torch.cuda.empty_cache()
+        print("[bench] form: backward", file=sys.stderr, flush=True)
+        forms["backward"] = form_backward(dev, fs, fw)
+        print("[bench] form: bf16", file=sys.stderr, flush=True)
+        forms["bf16"] = form_bf16(dev, fs, fw)
+        line["forms"] = forms
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(scene, cam)

@@ -94,7 +94,12 @@ typedef struct fs_opts {
     float t_stop;        /* a pixel stops before the surfel that would take its
                             transmittance below t_stop (1e-4) */
     int32_t batch;       /* list entries staged in LDS per step: 16 or 32 (0 = 32) */
+    int32_t schedule;    /* FS_SCHED_GRID: one workgroup per render block;
+                            FS_SCHED_PERSISTENT: a grid sized to the device pulls render
+                            blocks, longest tile list first, from a work queue */
 } fs_opts;
+
+enum { FS_SCHED_GRID = 0, FS_SCHED_PERSISTENT = 1 };
 
 /* Size of the record fs_preprocess writes per (view, surfel). */
 #define FS_RECORD_BYTES 96

@@ -26,6 +26,7 @@ bool valid_opts(const fs_opts* o) {
     if (!(o->alpha_min > 0.f) || !(o->alpha_max <= 1.f) || !(o->alpha_min < o->alpha_max)) return false;
     if (!(o->t_stop >= 0.f) || !(o->t_stop < 1.f)) return false;
     if (o->batch != 0 && o->batch != 16 && o->batch != 32) return false;
+    if (o->schedule != FS_SCHED_GRID && o->schedule != FS_SCHED_PERSISTENT) return false;
     return true;
 }
 
@@ -69,9 +70,13 @@ bool fs_workspace_layout(void* base, int64_t n, int32_t num_views, int64_t total
     w.keys_alt = static_cast<uint64_t*>(take(sizeof(uint64_t) * (size_t)(pair_capacity > 0 ? pair_capacity : 1)));
     w.vals_alt = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)(pair_capacity > 0 ? pair_capacity : 1)));
     const size_t sort_bytes = align_up(off, 256);
-    // render stage
+    // render stage: work queue of render blocks (at most 16 per tile: 8x8 blocks of a 32x32 tile)
     off = 0;
     w.render_ticket = static_cast<uint32_t*>(take(sizeof(uint32_t) * 16));
+    w.render_hist = static_cast<uint32_t*>(take(sizeof(uint32_t) * 64));
+    w.render_offs = static_cast<uint32_t*>(take(sizeof(uint32_t) * 64));
+    w.render_max_blocks = (total_tiles > 0 ? total_tiles : 1) * 16;
+    w.render_order = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)w.render_max_blocks));
     const size_t render_bytes = align_up(off, 256);
     size_t total = bin_bytes > sort_bytes ? bin_bytes : sort_bytes;
     total = total > render_bytes ? total : render_bytes;
@@ -147,7 +152,7 @@ fs_status fs_sort(uint64_t* keys, uint32_t* vals, int64_t pair_capacity, const i
     if (!num_pairs_dev || !workspace || !tile_ranges || total_tiles < 1 || pair_capacity < 0) return FS_ERR_ARG;
     if (pair_capacity > 0 && (!keys || !vals)) return FS_ERR_ARG;
     if (pair_capacity >= (int64_t(1) << 30) || total_tiles >= (int64_t(1) << 31)) return FS_ERR_ARG;
-    fs_opts dummy{16, 0, 0, 0, 1.f / 255.f, 0.99f, 1e-4f, 0};
+    fs_opts dummy{16, 0, 0, 0, 1.f / 255.f, 0.99f, 1e-4f, 0, 0};
     FsWorkspace ws;
     // the sort part of the layout only depends on capacity and tile count
     if (!fs_workspace_layout(workspace, 0, 1, total_tiles, pair_capacity, &dummy, &ws, nullptr)) return FS_ERR_ARG;
@@ -165,7 +170,10 @@ fs_status fs_render_forward(const void* records, const uint32_t* vals, const uin
     if (C > 1024) return FS_ERR_UNSUPPORTED;
     FsWorkspace ws;
     memset(&ws, 0, sizeof(ws));
-    (void)workspace;
+    if (opts->schedule == FS_SCHED_PERSISTENT) {
+        if (!workspace) return FS_ERR_ARG;
+        if (!fs_workspace_layout(workspace, 0, 1, total_tiles, 0, opts, &ws, nullptr)) return FS_ERR_ARG;
+    }
     return hip_status(fs_launch_render_forward(static_cast<const FsRecord*>(records), vals, tile_ranges, feats, C, n,
                                                cams_dev, num_views, total_tiles, *opts, out_feat, out_T, out_n,
                                                out_last, out_idx, counters, ws, stream));

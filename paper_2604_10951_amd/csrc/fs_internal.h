@@ -479,6 +479,10 @@ struct FsWorkspace {
     int npass;
     // render
     uint32_t* render_ticket;
+    uint32_t* render_hist;
+    uint32_t* render_offs;
+    uint32_t* render_order;
+    int64_t render_max_blocks;
 };
 
 bool fs_workspace_layout(void* base, int64_t n, int32_t num_views, int64_t total_tiles, int64_t pair_capacity,

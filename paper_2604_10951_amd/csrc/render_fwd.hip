@@ -73,31 +73,36 @@ struct RowVec {
     static constexpr int kElems = VEC ? 16 / (int)sizeof(FT) : 1;
 };
 
+template <int CPL, typename FT, int WAVES, int BG>
+struct FwdShared {
+    FsRecord rec[BG];
+    uint32_t recid[BG];
+    __align__(16) FT feat[BG][64 * CPL];
+    float w[WAVES][BG][64];
+    uint32_t used;
+    int active;
+    int list[BG];
+    uint32_t item;
+};
+
+// One render block: the walk over its tile's list (see the file comment).
 template <int CPL, typename FT, int WAVES, int BG, bool VEC>
-__global__ void __launch_bounds__(WAVES * 64)
-render_fwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restrict__ vals,
-                  const uint32_t* __restrict__ ranges, const FT* __restrict__ feats, int C, int64_t n,
-                  int64_t num_records, const fs_camera* __restrict__ cams, int num_views, int S, fs_opts o,
-                  float* __restrict__ out_feat, float* __restrict__ out_T, int32_t* __restrict__ out_n,
-                  int32_t* __restrict__ out_last, int32_t* __restrict__ out_idx, uint64_t* __restrict__ counters) {
+FS_DEV void render_block(int64_t block, FwdShared<CPL, FT, WAVES, BG>& sm, const FsRecord* __restrict__ records,
+                         const uint32_t* __restrict__ vals, const uint32_t* __restrict__ ranges,
+                         const FT* __restrict__ feats, int C, int64_t n, int64_t num_records,
+                         const fs_camera* __restrict__ cams, int num_views, int S, const fs_opts& o,
+                         float* __restrict__ out_feat, float* __restrict__ out_T, int32_t* __restrict__ out_n,
+                         int32_t* __restrict__ out_last, int32_t* __restrict__ out_idx,
+                         uint64_t* __restrict__ counters) {
     constexpr int NT = WAVES * 64;
     constexpr int kChunk = 64 * CPL;
     constexpr int RB = WAVES == 1 ? 8 : 16;
     constexpr int kQ = FS_RECORD_BYTES / 16;                 // float4 per record
     constexpr int kRecSlots = (BG * kQ + NT - 1) / NT;       // record float4 per thread
     constexpr int kVE = RowVec<FT, VEC>::kElems;             // feature elements per vector load
-
-    __shared__ FsRecord s_rec[BG];
-    __shared__ uint32_t s_recid[BG];
-    __shared__ __align__(16) FT s_feat[BG][kChunk];
-    __shared__ float s_w[WAVES][BG][64];
-    __shared__ uint32_t s_used;
-    __shared__ int s_active;
-    __shared__ int s_list[BG];
-
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const BlockPos bp = locate_block(blockIdx.x, S, RB, cams, num_views);
-    if (!bp.valid) return;
+    const BlockPos bp = locate_block(block, S, RB, cams, num_views);
+    if (!bp.valid) return;   // uniform across the workgroup
     const fs_camera& cam = cams[bp.view];
     const int chunk = blockIdx.y;
     const int c0 = chunk * kChunk;
@@ -148,8 +153,8 @@ render_fwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
         const int nb = (int)(end - b0 < (uint32_t)BG ? end - b0 : (uint32_t)BG);
         // 1. stage the prefetched records
         if (tid == 0) {
-            s_used = 0u;
-            s_active = 0;
+            sm.used = 0u;
+            sm.active = 0;
         }
 #pragma unroll
         for (int j = 0; j < kRecSlots; ++j) {
@@ -164,8 +169,8 @@ render_fwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
                     if (q == 4) v4.w = __int_as_float((int)0xbff00000);   // k2 = -1: never accepted
                     if (q == 5) v4.z = __int_as_float(1);                 // empty box
                 }
-                reinterpret_cast<float4*>(&s_rec[e])[q] = v4;
-                if (q == 0) s_recid[e] = rid;
+                reinterpret_cast<float4*>(&sm.rec[e])[q] = v4;
+                if (q == 0) sm.recid[e] = rid;
             }
         }
         __syncthreads();
@@ -174,7 +179,7 @@ render_fwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
         uint32_t mask = 0u;
         if (!__all(done)) {
             for (int e = 0; e < nb; ++e) {
-                const FsRecord& r = s_rec[e];
+                const FsRecord& r = sm.rec[e];
                 if (r.x1 < wx0 || r.x0 > wx0 + 7 || r.y1 < wy0 || r.y0 > wy0 + 7) continue;
                 if (!done) {
                     const FsResp rs = fs_response(r, (double)(px - r.ax), (double)(py - r.ay));
@@ -185,10 +190,10 @@ render_fwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
                         if (Tn < t_stop) {
                             done = true;
                         } else {
-                            s_w[wave][e][lane] = (float)((double)alpha * T);
+                            sm.w[wave][e][lane] = (float)((double)alpha * T);
                             mask |= 1u << e;
                             T = Tn;
-                            if (write_idx) out_idx[pix * K + cnt] = (int32_t)s_recid[e];
+                            if (write_idx) out_idx[pix * K + cnt] = (int32_t)sm.recid[e];
                             ++cnt;
                             last = (int)(b0 + e);
                             if (K > 0 && cnt == K) done = true;
@@ -202,14 +207,14 @@ render_fwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
         const uint64_t active_px = __ballot(mask != 0u);
         const bool wactive = !__all(done);
         if (lane == 0) {
-            if (wused) atomicOr(&s_used, wused);
-            if (wactive) atomicAdd(&s_active, 1);
+            if (wused) atomicOr(&sm.used, wused);
+            if (wactive) atomicAdd(&sm.active, 1);
         }
         __syncthreads();
-        const uint32_t used = s_used;
-        const int active = s_active;   // latched: wave 0 re-zeroes both at the next batch
+        const uint32_t used = sm.used;
+        const int active = sm.active;   // latched: wave 0 re-zeroes both at the next batch
         const int nu = __popc(used);
-        if (tid < BG && ((used >> tid) & 1u)) s_list[__popc(used & ((1u << tid) - 1u))] = tid;
+        if (tid < BG && ((used >> tid) & 1u)) sm.list[__popc(used & ((1u << tid) - 1u))] = tid;
         walked += (uint32_t)nb;
         fetched += (uint32_t)nu;
         __syncthreads();
@@ -217,7 +222,7 @@ render_fwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
         //    before the first LDS store
         if (VEC) {
             // direct global -> LDS loads, 16 B per lane, rows packed in the
-            // order of the compacted list (row j of the batch at s_feat[j])
+            // order of the compacted list (row j of the batch at sm.feat[j])
             constexpr int kRowBytes = kChunk * (int)sizeof(FT);
             constexpr int kLanesPerRow = kRowBytes / 16;
             constexpr int kRowsPerInst = 64 / kLanesPerRow;
@@ -226,10 +231,10 @@ render_fwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
             for (int i = wave; i < ninst; i += WAVES) {
                 const int row = i * kRowsPerInst + lrow;
                 if (row < nu && lcol * kVE < clen) {
-                    const int64_t sidx = fs_surfel_of(s_recid[s_list[row]], n);
+                    const int64_t sidx = fs_surfel_of(sm.recid[sm.list[row]], n);
                     const FT* src = feats + sidx * C + c0 + lcol * kVE;
                     __builtin_amdgcn_global_load_lds(
-                        (const void*)src, (__attribute__((address_space(3))) void*)&s_feat[i * kRowsPerInst][0], 16,
+                        (const void*)src, (__attribute__((address_space(3))) void*)&sm.feat[i * kRowsPerInst][0], 16,
                         0, 0);
                 }
             }
@@ -238,9 +243,9 @@ render_fwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
             for (int t = tid; t < nu * kChunk; t += NT) {
                 const int j = t / kChunk, c = t - j * kChunk;
                 if (c < clen) {
-                    const int e = s_list[j];
-                    const int64_t sidx = fs_surfel_of(s_recid[e], n);
-                    s_feat[j][c] = feats[sidx * C + c0 + c];
+                    const int e = sm.list[j];
+                    const int64_t sidx = fs_surfel_of(sm.recid[e], n);
+                    sm.feat[j][c] = feats[sidx * C + c0 + c];
                 }
             }
         }
@@ -254,15 +259,15 @@ render_fwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
                     const int e = __builtin_ctz(m);
                     m &= m - 1u;
                     const int j = __popc(used & ((1u << e) - 1u));   // row slot of entry e
-                    const float w = s_w[wave][e][p];
+                    const float w = sm.w[wave][e][p];
                     if (CPL == 2 && sizeof(FT) == 4) {
-                        const float2 f = *reinterpret_cast<const float2*>(&s_feat[j][lane * 2]);
+                        const float2 f = *reinterpret_cast<const float2*>(&sm.feat[j][lane * 2]);
                         acc[p][0] = fmaf(w, f.x, acc[p][0]);
                         acc[p][CPL - 1] = fmaf(w, f.y, acc[p][CPL - 1]);
                     } else {
 #pragma unroll
                         for (int c = 0; c < CPL; ++c)
-                            acc[p][c] = fmaf(w, feat_to_f32(s_feat[j][lane * CPL + c]), acc[p][c]);
+                            acc[p][c] = fmaf(w, feat_to_f32(sm.feat[j][lane * CPL + c]), acc[p][c]);
                     }
                 }
             }
@@ -305,25 +310,126 @@ render_fwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
     }
 }
 
+// Grid launch (order == nullptr): workgroup b renders block b.  Persistent
+// launch: workgroups take positions of `order` (blocks sorted by list
+// length, longest first) from an atomic ticket until the queue is empty.
+template <int CPL, typename FT, int WAVES, int BG, bool VEC>
+__global__ void __launch_bounds__(WAVES * 64)
+render_fwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restrict__ vals,
+                  const uint32_t* __restrict__ ranges, const FT* __restrict__ feats, int C, int64_t n,
+                  int64_t num_records, const fs_camera* __restrict__ cams, int num_views, int S, fs_opts o,
+                  float* __restrict__ out_feat, float* __restrict__ out_T, int32_t* __restrict__ out_n,
+                  int32_t* __restrict__ out_last, int32_t* __restrict__ out_idx, uint64_t* __restrict__ counters,
+                  const uint32_t* __restrict__ order, uint32_t* __restrict__ ticket, uint32_t nblocks) {
+    __shared__ FwdShared<CPL, FT, WAVES, BG> sm;
+    if (order == nullptr) {
+        render_block<CPL, FT, WAVES, BG, VEC>(blockIdx.x, sm, records, vals, ranges, feats, C, n, num_records, cams,
+                                              num_views, S, o, out_feat, out_T, out_n, out_last, out_idx, counters);
+        return;
+    }
+    for (;;) {
+        __syncthreads();   // every wave is done with the previous item (and sm.item)
+        if (threadIdx.x == 0) sm.item = atomicAdd(ticket, 1u);
+        __syncthreads();
+        const uint32_t it = sm.item;
+        if (it >= nblocks) break;
+        render_block<CPL, FT, WAVES, BG, VEC>(order[it], sm, records, vals, ranges, feats, C, n, num_records, cams,
+                                              num_views, S, o, out_feat, out_T, out_n, out_last, out_idx, counters);
+    }
+}
+
+// Work order for the persistent launch: blocks bucketed by 4 log2(1 + list
+// length) (64 buckets), longest bucket first.
+FS_DEV int cost_bucket(uint32_t len) {
+    const float b = 4.f * __log2f(1.f + (float)len);
+    const int k = (int)b;
+    return 63 - (k > 63 ? 63 : k);
+}
+
+__global__ void order_hist_kernel(const uint32_t* __restrict__ ranges, int sb2, uint32_t nblocks,
+                                  uint32_t* __restrict__ hist, uint32_t* __restrict__ ticket) {
+    __shared__ uint32_t h[64];
+    if (threadIdx.x < 64) h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < nblocks) {
+        const uint32_t t = b / sb2;
+        atomicAdd(&h[cost_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+    if (b == 0) *ticket = 0u;
+}
+
+__global__ void order_scan_kernel(uint32_t* __restrict__ hist, uint32_t* __restrict__ offs) {
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int k = 0; k < 64; ++k) {
+            offs[k] = acc;
+            acc += hist[k];
+            hist[k] = 0u;   // ready for the next frame
+        }
+    }
+}
+
+__global__ void order_scatter_kernel(const uint32_t* __restrict__ ranges, int sb2, uint32_t nblocks,
+                                     uint32_t* __restrict__ offs, uint32_t* __restrict__ order) {
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblocks) return;
+    const uint32_t t = b / sb2;
+    const uint32_t pos = atomicAdd(&offs[cost_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
+    if (pos < nblocks) order[pos] = b;
+}
+
+__global__ void zero_u32_kernel(uint32_t* p, int count) {
+    if ((int)threadIdx.x < count) p[threadIdx.x] = 0u;
+}
+
+int device_cus() {
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+    }
+    return cus;
+}
+
+
 template <int CPL, typename FT, int WAVES, int BG>
 hipError_t launch(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges, const void* feats, int C,
                   int64_t n, const fs_camera* cams, int num_views, int64_t total_tiles, const fs_opts& o,
                   float* out_feat, float* out_T, int32_t* out_n, int32_t* out_last, int32_t* out_idx,
-                  uint64_t* counters, hipStream_t s) {
+                  uint64_t* counters, const FsWorkspace& ws, hipStream_t s) {
     constexpr int RB = WAVES == 1 ? 8 : 16;
     const int sb = o.tile / RB;
     const int64_t blocks = total_tiles * sb * sb;
     const int chunks = (C + 64 * CPL - 1) / (64 * CPL);
     const bool vec = (C % (16 / (int)sizeof(FT))) == 0;
-    dim3 grid((unsigned)blocks, (unsigned)chunks);
-    if (vec)
-        hipLaunchKernelGGL((render_fwd_kernel<CPL, FT, WAVES, BG, true>), grid, dim3(WAVES * 64), 0, s, records, vals,
-                           ranges, static_cast<const FT*>(feats), C, n, n * num_views, cams, num_views, o.tile, o,
-                           out_feat, out_T, out_n, out_last, out_idx, counters);
-    else
-        hipLaunchKernelGGL((render_fwd_kernel<CPL, FT, WAVES, BG, false>), grid, dim3(WAVES * 64), 0, s, records,
-                           vals, ranges, static_cast<const FT*>(feats), C, n, n * num_views, cams, num_views, o.tile,
-                           o, out_feat, out_T, out_n, out_last, out_idx, counters);
+    auto kern = vec ? render_fwd_kernel<CPL, FT, WAVES, BG, true> : render_fwd_kernel<CPL, FT, WAVES, BG, false>;
+    if (o.schedule == FS_SCHED_PERSISTENT && chunks == 1 && blocks <= ws.render_max_blocks) {
+        const uint32_t nb = (uint32_t)blocks;
+        const unsigned g = (unsigned)((nb + 255) / 256);
+        hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, ws.render_hist, 64);
+        hipLaunchKernelGGL(order_hist_kernel, dim3(g), dim3(256), 0, s, ranges, sb * sb, nb, ws.render_hist,
+                           ws.render_ticket);
+        hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, s, ws.render_hist, ws.render_offs);
+        hipLaunchKernelGGL(order_scatter_kernel, dim3(g), dim3(256), 0, s, ranges, sb * sb, nb, ws.render_offs,
+                           ws.render_order);
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), WAVES * 64, 0) !=
+                hipSuccess || per_cu < 1)
+            per_cu = 1;
+        int64_t grid = (int64_t)device_cus() * per_cu;
+        if (grid > blocks) grid = blocks;
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(WAVES * 64), 0, s, records, vals, ranges,
+                           static_cast<const FT*>(feats), C, n, n * num_views, cams, num_views, o.tile, o, out_feat,
+                           out_T, out_n, out_last, out_idx, counters, ws.render_order, ws.render_ticket, nb);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks, (unsigned)chunks), dim3(WAVES * 64), 0, s, records, vals, ranges,
+                       static_cast<const FT*>(feats), C, n, n * num_views, cams, num_views, o.tile, o, out_feat,
+                       out_T, out_n, out_last, out_idx, counters, (const uint32_t*)nullptr, (uint32_t*)nullptr, 0u);
     return hipGetLastError();
 }
 
@@ -331,12 +437,20 @@ template <int CPL, typename FT>
 hipError_t launch_waves(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges, const void* feats,
                         int C, int64_t n, const fs_camera* cams, int num_views, int64_t total_tiles,
                         const fs_opts& o, float* out_feat, float* out_T, int32_t* out_n, int32_t* out_last,
-                        int32_t* out_idx, uint64_t* counters, hipStream_t s) {
-    if (o.tile == 8)
-        return launch<CPL, FT, 1, 32>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o, out_feat,
-                                      out_T, out_n, out_last, out_idx, counters, s);
-    return launch<CPL, FT, 4, 32>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o, out_feat,
-                                  out_T, out_n, out_last, out_idx, counters, s);
+                        int32_t* out_idx, uint64_t* counters, const FsWorkspace& ws, hipStream_t s) {
+    // 8x8 tiles: one-wave blocks; larger tiles: 16x16 blocks of four waves sharing the list staging
+    const bool small = o.tile == 8;
+    const bool bg16 = o.batch == 16;
+#define FS_LAUNCH(W, B)                                                                                          \
+    return launch<CPL, FT, W, B>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o, out_feat, \
+                                 out_T, out_n, out_last, out_idx, counters, ws, s)
+    if (small) {
+        if (bg16) FS_LAUNCH(1, 16);
+        FS_LAUNCH(1, 32);
+    }
+    if (bg16) FS_LAUNCH(4, 16);
+    FS_LAUNCH(4, 32);
+#undef FS_LAUNCH
 }
 
 }  // namespace
@@ -346,17 +460,15 @@ hipError_t fs_launch_render_forward(const FsRecord* records, const uint32_t* val
                                     int64_t total_tiles, const fs_opts& o, float* out_feat, float* out_T,
                                     int32_t* out_n, int32_t* out_last, int32_t* out_idx, uint64_t* counters,
                                     const FsWorkspace& ws, hipStream_t s) {
-    (void)ws;
     if (total_tiles == 0) return hipSuccess;
     const bool bf16 = o.feat_dtype == FS_FEAT_BF16;
-    if (C <= 64) {
+    if (C <= 64)
         return bf16 ? launch_waves<1, uint16_t>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o,
-                                                out_feat, out_T, out_n, out_last, out_idx, counters, s)
+                                                out_feat, out_T, out_n, out_last, out_idx, counters, ws, s)
                     : launch_waves<1, float>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o,
-                                             out_feat, out_T, out_n, out_last, out_idx, counters, s);
-    }
+                                             out_feat, out_T, out_n, out_last, out_idx, counters, ws, s);
     return bf16 ? launch_waves<2, uint16_t>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o,
-                                            out_feat, out_T, out_n, out_last, out_idx, counters, s)
+                                            out_feat, out_T, out_n, out_last, out_idx, counters, ws, s)
                 : launch_waves<2, float>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o,
-                                         out_feat, out_T, out_n, out_last, out_idx, counters, s);
+                                         out_feat, out_T, out_n, out_last, out_idx, counters, ws, s);
 }

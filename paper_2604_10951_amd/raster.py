@@ -66,8 +66,8 @@ class Rasterizer:
 
     def __init__(self, cams, *, tile: int = 16, topk: int = 0, tile_mode: str = "precise",
                  feat_dtype: str = "f32", alpha_min: float = ALPHA_MIN, alpha_max: float = ALPHA_MAX,
-                 t_stop: float = T_STOP, batch: int = 0, device: str | torch.device = "cuda",
-                 pair_capacity: int = 0):
+                 t_stop: float = T_STOP, batch: int = 0, schedule: str = "grid",
+                 device: str | torch.device = "cuda", pair_capacity: int = 0):
         self.lib = L.load()
         self.device = torch.device(device)
         self.cams = list(cams) if isinstance(cams, (list, tuple)) else [cams]
@@ -75,7 +75,8 @@ class Rasterizer:
         mode = {"precise": L.FS_TILES_PRECISE, "bbox": L.FS_TILES_BBOX}[tile_mode]
         dt = {"f32": L.FS_FEAT_F32, "bf16": L.FS_FEAT_BF16}[feat_dtype]
         self.feat_dtype = feat_dtype
-        self.opts = L.make_opts(tile, topk, mode, dt, alpha_min, alpha_max, t_stop, batch)
+        sched = {"grid": L.FS_SCHED_GRID, "persistent": L.FS_SCHED_PERSISTENT}[schedule]
+        self.opts = L.make_opts(tile, topk, mode, dt, alpha_min, alpha_max, t_stop, batch, sched)
         self.cam_arr, self.total_tiles, self.total_pixels = L.make_cameras(self.cams, tile)
         raw = bytes(ctypes.string_at(ctypes.addressof(self.cam_arr), ctypes.sizeof(self.cam_arr)))
         self.cams_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)
@@ -86,6 +87,17 @@ class Rasterizer:
     @property
     def topk(self) -> int:
         return int(self.opts.topk)
+
+    def set_cameras(self, cams) -> None:
+        """Replace the camera poses/intrinsics in place (same resolutions), so a
+        captured frame graph renders the new views on its next replay."""
+        cams = list(cams) if isinstance(cams, (list, tuple)) else [cams]
+        if [(c.width, c.height) for c in cams] != [(c.width, c.height) for c in self.cams]:
+            raise ValueError("set_cameras keeps the view resolutions")
+        arr, tt, tp = L.make_cameras(cams, int(self.opts.tile))
+        raw = bytes(ctypes.string_at(ctypes.addressof(arr), ctypes.sizeof(arr)))
+        self.cams_dev.copy_(torch.frombuffer(bytearray(raw), dtype=torch.uint8))
+        self.cams, self.cam_arr = cams, arr
 
     # -- buffers ------------------------------------------------------------
     def _ensure(self, n: int, capacity: int):
@@ -248,3 +260,39 @@ def scene_tensors(scene, device="cuda", feat_dtype: str = "f32"):
     if feat_dtype == "bf16":
         feats = feats.to(torch.bfloat16).contiguous()
     return t(scene.means), t(scene.scales), t(scene.quats), t(scene.opacity), feats
+
+
+class FrameGraph:
+    """One whole frame (preprocess -> bin -> sort -> render) captured as a HIP
+    graph and replayed.  The pair count stays on the device (no host
+    synchronisation inside the frame); launches are sized by the pair
+    capacity established by an eager frame first.  Camera poses can change
+    between replays through ``Rasterizer.set_cameras``."""
+
+    def __init__(self, rast: Rasterizer, tensors, *, want_last: bool = False, headroom: float = 1.25):
+        self.rast = rast
+        self.tensors = tensors
+        frame = rast.render(*tensors)                      # sizes the buffers
+        need = int(frame.num_pairs * headroom) + 4096
+        if need > rast.capacity:
+            rast._ensure(tensors[0].shape[0], need)
+            rast.render(*tensors)
+        self.out = rast.alloc_out(tensors[4].shape[1], want_last=want_last)
+        # warm up on a side stream (first launches may initialise the runtime)
+        s = torch.cuda.Stream(device=rast.device)
+        s.wait_stream(torch.cuda.current_stream(rast.device))
+        with torch.cuda.stream(s):
+            rast.render_nosync(*tensors, self.out)
+        torch.cuda.current_stream(rast.device).wait_stream(s)
+        torch.cuda.synchronize(rast.device)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            rast.render_nosync(*tensors, self.out)
+        torch.cuda.synchronize(rast.device)
+
+    def replay(self) -> dict:
+        self.graph.replay()
+        return self.out
+
+    def pairs_fit(self) -> bool:
+        return self.rast.pairs_fit()
