@@ -85,9 +85,9 @@ def _time_frames(rast, tens, steps, warmup):
     return a.elapsed_time(b) / steps
 
 
-def _plain(cams, tens, dev, steps, warmup, topk=0, tile=8):
+def _plain(cams, tens, dev, steps, warmup, topk=0, tile=8, schedule="grid"):
     """Plain FP32 full blend (the comparison point of every form)."""
-    rast = raster.Rasterizer(cams, tile=tile, topk=topk, device=dev)
+    rast = raster.Rasterizer(cams, tile=tile, topk=topk, schedule=schedule, device=dev)
     rast.render(*tens)
     ms = _time_frames(rast, tens, steps, warmup)
     del rast
@@ -101,11 +101,11 @@ def form_bf16(dev, steps, warmup):
     res = {"workload": "1M surfels, 1280x720, C=256, Top-K K=16, 8x8 tiles"}
     t32 = raster.scene_tensors(scene, dev)
     res["plain_f32_full_ms"] = _plain(cam, t32, dev, steps, warmup)
-    res["f32_topk_ms"] = _plain(cam, t32, dev, steps, warmup, topk=16)
+    res["f32_topk_ms"] = _plain(cam, t32, dev, steps, warmup, topk=16, schedule="split")
     t16 = raster.scene_tensors(scene, dev, "bf16")
     del t32
     torch.cuda.empty_cache()
-    rast = raster.Rasterizer(cam, tile=8, topk=16, feat_dtype="bf16", device=dev)
+    rast = raster.Rasterizer(cam, tile=8, topk=16, feat_dtype="bf16", schedule="split", device=dev)
     rast.render(*t16)
     res["bf16_topk_ms"] = _time_frames(rast, t16, steps, warmup)
     res["bf16_vs_plain_f32_full"] = res["plain_f32_full_ms"] / res["bf16_topk_ms"]
@@ -182,13 +182,16 @@ def form_backward(dev, steps, warmup):
     return res
 
 
-def measured_traffic():
-    """HBM bytes per Top-K render launch from the committed FETCH_SIZE /
-    WRITE_SIZE counter runs, if the render sources are unchanged since."""
+def measured_traffic(schedule):
+    """HBM bytes per Top-K render (all its kernels) from the committed
+    FETCH_SIZE / WRITE_SIZE counter runs, if the render sources are unchanged
+    since and the runs used this schedule."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "render_fwd_topk_headline_traffic.json")
     try:
         rec = json.load(open(path))
+        if rec.get("schedule", "grid") != schedule:
+            return None
         h = hashlib.sha256()
         for p in rec["sources"]:
             h.update(open(os.path.join(ROOT, p), "rb").read())
@@ -227,6 +230,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tile", type=int, default=TILE)
+    ap.add_argument("--schedule", default="split", choices=("grid", "persistent", "split"),
+                    help="render schedule of the Top-K frames (the full blend uses 'grid')")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 / batched / backward forms")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer 3 times (reference for HBM byte counters)")
@@ -250,7 +255,8 @@ def main():
 
     results = {}
     for name, topk in (("topk", K), ("full", 0)):
-        rast = raster.Rasterizer(cam, tile=args.tile, topk=topk, device=dev)
+        rast = raster.Rasterizer(cam, tile=args.tile, topk=topk, schedule=args.schedule if topk else "grid",
+                                 device=dev)
         fr = rast.render(*tens)           # establishes the pair capacity
         P = fr.num_pairs
         out = rast.alloc_out(C)
@@ -281,16 +287,19 @@ def main():
         "data": "synthetic (seeded clustered surfel scene standing in for ScanNet-V2 reconstructions)",
         "config": {"workload": f"1M surfels, 1280x720, C=128 float32, Top-K K=8, {args.tile}x{args.tile} tiles, whole path "
                                "(preprocess+bin+sort+render) per frame", "surfels": scene.n, "width": W,
-                   "height": H, "channels": C, "topk": K, "tile": args.tile, "parallelism": "single GPU"},
+                   "height": H, "channels": C, "topk": K, "tile": args.tile, "schedule": args.schedule,
+                   "parallelism": "single GPU"},
         "full_blend": {"value": 1000.0 / full["ms"], "unit": "FPS", "ms_per_step": full["ms"],
                        "render_ms": full["render_ms"], "stages_ms": full["stages_ms"]},
         "stages_ms": top["stages_ms"],
         "topk_speedup_vs_full": full["ms"] / top["ms"],
         "pairs": top["P"],
         "render_counters": {"topk": top["counters"], "full": full["counters"]},
-        "roofline": {"kernel": "render_fwd_kernel (Top-K)", "bound": "hbm", "achieved": achieved,
+        "roofline": {"kernel": ("render forward, Top-K: topk_select_kernel + topk_gather_kernel"
+                                if args.schedule == "split" else "render_fwd_kernel (Top-K)"),
+                     "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if args.tile == TILE else None,
+                     "traffic": measured_traffic(args.schedule) if args.tile == TILE else None,
                      "algorithmic_bytes": top["render_bytes"], "avg_launch_ms": top["render_ms"]},
         "frame_hbm_frac": frame_bytes(scene.n, top["P"], top["counters"], H, W, C) / (top["ms"] * 1e-3) / 1e9
                           / HBM_PEAK_GBS,

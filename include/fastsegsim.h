@@ -96,10 +96,14 @@ typedef struct fs_opts {
     int32_t batch;       /* list entries staged in LDS per step: 16 or 32 (0 = 32) */
     int32_t schedule;    /* FS_SCHED_GRID: one workgroup per render block;
                             FS_SCHED_PERSISTENT: a grid sized to the device pulls render
-                            blocks, longest tile list first, from a work queue */
+                            blocks, longest tile list first, from a work queue;
+                            FS_SCHED_SPLIT (topk > 0 only): a selection pass writes every
+                            pixel's Top-K (surfel, weight) list to the workspace, then a
+                            gather pass blends the feature rows; same results as the
+                            other two, bit for bit */
 } fs_opts;
 
-enum { FS_SCHED_GRID = 0, FS_SCHED_PERSISTENT = 1 };
+enum { FS_SCHED_GRID = 0, FS_SCHED_PERSISTENT = 1, FS_SCHED_SPLIT = 2 };
 
 /* Size of the record fs_preprocess writes per (view, surfel). */
 #define FS_RECORD_BYTES 96
@@ -184,8 +188,9 @@ fs_status fs_sort(uint64_t* keys, uint32_t* vals, int64_t pair_capacity, const i
  *   out_idx    optional out, total_pixels x topk int32 record indices of the
  *              blended surfels front to back, -1 padded (topk > 0 only)
  *   counters   optional in/out, 4 uint64 added to: [0] list entries walked
- *              (over all blocks), [1] feature rows fetched (one per block and
- *              used entry), [2] blended (pixel, surfel) pairs, [3] blocks run
+ *              (over all 8x8 or 16x16 render blocks), [1] feature rows the
+ *              blocks need (one per block and entry blended by any of its
+ *              pixels), [2] blended (pixel, surfel) pairs, [3] blocks run
  */
 fs_status fs_render_forward(const void* records, const uint32_t* vals, const uint32_t* tile_ranges, const void* feats,
                             int32_t C, int64_t n, const fs_camera* cams_dev, int32_t num_views, int64_t total_tiles,

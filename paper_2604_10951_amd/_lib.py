@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libfastsegsim.so")
 FS_OK, FS_ERR_ARG, FS_ERR_CAPACITY, FS_ERR_HIP, FS_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
 FS_TILES_PRECISE, FS_TILES_BBOX = 0, 1
 FS_FEAT_F32, FS_FEAT_BF16 = 0, 1
-FS_SCHED_GRID, FS_SCHED_PERSISTENT = 0, 1
+FS_SCHED_GRID, FS_SCHED_PERSISTENT, FS_SCHED_SPLIT = 0, 1, 2
 FS_RECORD_BYTES = 96
 FS_GRAD_RECORD_FLOATS = 12
 

@@ -2,8 +2,9 @@
 
 Times whole frames (preprocess -> bin -> sort -> render) of the caller's own
 scene and views for every candidate binning tile size (8, 16, 32), LDS batch
-of list entries (16, 32) and render schedule (one workgroup per block, or a
-persistent longest-list-first work queue), and returns the fastest.  Results
+of list entries (16, 32) and render schedule (one workgroup per block, a
+persistent longest-list-first work queue, or -- for Top-K -- the split
+selection + gather passes, which take no batch size), and returns the fastest.  Results
 are cached in a JSON file keyed by the workload's shape.
 """
 from __future__ import annotations
@@ -18,7 +19,7 @@ from .raster import Rasterizer
 
 TILES = (8, 16, 32)
 BATCHES = (16, 32)
-SCHEDULES = ("grid", "persistent")
+SCHEDULES = ("grid", "persistent", "split")
 
 
 def _cache_path() -> str:
@@ -66,7 +67,8 @@ def tune(cams, tensors, *, topk: int, feat_dtype: str = "f32", steps: int = 5, u
             cache = {}
         if key in cache:
             return dict(cache[key], cached=True)
-    cands = candidates or list(itertools.product(TILES, BATCHES, SCHEDULES))
+    cands = candidates or [(t, b, s) for t, b, s in itertools.product(TILES, BATCHES, SCHEDULES)
+                           if s != "split" or (topk > 0 and b == BATCHES[-1])]
     trials = []
     for tile, batch, schedule in cands:
         ms = time_config(cams, tensors, tile=tile, batch=batch, schedule=schedule, topk=topk,

@@ -26,7 +26,9 @@ bool valid_opts(const fs_opts* o) {
     if (!(o->alpha_min > 0.f) || !(o->alpha_max <= 1.f) || !(o->alpha_min < o->alpha_max)) return false;
     if (!(o->t_stop >= 0.f) || !(o->t_stop < 1.f)) return false;
     if (o->batch != 0 && o->batch != 16 && o->batch != 32) return false;
-    if (o->schedule != FS_SCHED_GRID && o->schedule != FS_SCHED_PERSISTENT) return false;
+    if (o->schedule != FS_SCHED_GRID && o->schedule != FS_SCHED_PERSISTENT && o->schedule != FS_SCHED_SPLIT)
+        return false;
+    if (o->schedule == FS_SCHED_SPLIT && o->topk < 1) return false;
     return true;
 }
 
@@ -39,7 +41,6 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // workspace are ordered on one stream, so the regions may overlap.
 bool fs_workspace_layout(void* base, int64_t n, int32_t num_views, int64_t total_tiles, int64_t pair_capacity,
                          const fs_opts* opts, FsWorkspace* ws, size_t* bytes) {
-    (void)opts;
     if (n < 0 || num_views < 1 || total_tiles < 0 || pair_capacity < 0) return false;
     FsWorkspace w;
     memset(&w, 0, sizeof(w));
@@ -77,6 +78,13 @@ bool fs_workspace_layout(void* base, int64_t n, int32_t num_views, int64_t total
     w.render_offs = static_cast<uint32_t*>(take(sizeof(uint32_t) * 64));
     w.render_max_blocks = (total_tiles > 0 ? total_tiles : 1) * 16;
     w.render_order = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)w.render_max_blocks));
+    if (opts && opts->schedule == FS_SCHED_SPLIT && opts->topk > 0) {
+        const int64_t sb = opts->tile / 8;
+        w.topk_pair_slots = (total_tiles > 0 ? total_tiles : 1) * sb * sb * 64 * (int64_t)opts->topk;
+        w.topk_pairs = static_cast<uint2*>(take(sizeof(uint2) * (size_t)w.topk_pair_slots));
+        w.topk_rows = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)w.topk_pair_slots));
+        w.topk_nrows = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)(w.topk_pair_slots / (64 * opts->topk))));
+    }
     const size_t render_bytes = align_up(off, 256);
     size_t total = bin_bytes > sort_bytes ? bin_bytes : sort_bytes;
     total = total > render_bytes ? total : render_bytes;
@@ -170,10 +178,14 @@ fs_status fs_render_forward(const void* records, const uint32_t* vals, const uin
     if (C > 1024) return FS_ERR_UNSUPPORTED;
     FsWorkspace ws;
     memset(&ws, 0, sizeof(ws));
-    if (opts->schedule == FS_SCHED_PERSISTENT) {
+    if (opts->schedule != FS_SCHED_GRID) {
         if (!workspace) return FS_ERR_ARG;
         if (!fs_workspace_layout(workspace, 0, 1, total_tiles, 0, opts, &ws, nullptr)) return FS_ERR_ARG;
     }
+    if (opts->schedule == FS_SCHED_SPLIT)
+        return hip_status(fs_launch_render_topk_split(static_cast<const FsRecord*>(records), vals, tile_ranges, feats,
+                                                      C, n, cams_dev, num_views, total_tiles, *opts, out_feat, out_T,
+                                                      out_n, out_last, out_idx, counters, ws, stream));
     return hip_status(fs_launch_render_forward(static_cast<const FsRecord*>(records), vals, tile_ranges, feats, C, n,
                                                cams_dev, num_views, total_tiles, *opts, out_feat, out_T, out_n,
                                                out_last, out_idx, counters, ws, stream));

@@ -69,29 +69,44 @@ bin_kernel(const float* __restrict__ means, const float* __restrict__ scales, co
         if (w < wave) wave_excl += s_wave[w];
         total += s_wave[w];
     }
-    if (tid == 0) {
+    if (wave == 0) {
+        // decoupled look-back, one wave: lane l reads the status of partition
+        // j - l, so each round trip covers 64 predecessors
         uint64_t prefix = 0;
         if (part == 0) {
-            __hip_atomic_store(status + part, kFlagPre | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                __hip_atomic_store(status + part, kFlagPre | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            __hip_atomic_store(status + part, kFlagAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                __hip_atomic_store(status + part, kFlagAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             int64_t j = part - 1;
             while (true) {
-                const uint64_t st = __hip_atomic_load(status + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int64_t idx = j - lane;
+                const uint64_t st = idx >= 0 ? __hip_atomic_load(status + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                             : kFlagPre;   // before partition 0: an empty inclusive prefix
                 const uint64_t flag = st & ~kValMask;
-                if (flag == 0) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                prefix += st & kValMask;
-                if (flag == kFlagPre) break;
-                --j;
+                const uint64_t notready = __ballot(flag == 0);
+                const uint64_t pre = __ballot(flag == kFlagPre);
+                const int limit = notready ? __builtin_ctzll(notready) : 64;
+                const int first_pre = pre ? __builtin_ctzll(pre) : 64;
+                const bool found = first_pre < limit;
+                const int take = found ? first_pre + 1 : limit;     // lanes [0, take) are summed
+                uint64_t v = lane < take ? (st & kValMask) : 0ull;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) v += __shfl_xor(v, d, 64);
+                prefix += v;
+                if (found) break;
+                j -= take;
+                if (take == 0) __builtin_amdgcn_s_sleep(1);
             }
-            __hip_atomic_store(status + part, kFlagPre | (prefix + total), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                __hip_atomic_store(status + part, kFlagPre | (prefix + total), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_prefix = prefix;
-        if (part == parts - 1) *num_pairs = (int64_t)(prefix + total);
+        if (lane == 0) {
+            s_prefix = prefix;
+            if (part == parts - 1) *num_pairs = (int64_t)(prefix + total);
+        }
     }
     __syncthreads();
     uint64_t off = s_prefix + wave_excl + (incl - sum);

@@ -459,6 +459,36 @@ FS_DEV int fs_view_of_tile(const fs_camera* cams, int num_views, int64_t tile) {
     return lo;
 }
 
+// Render block b of a frame: tile b / (S / RB)^2, sub-block b % (S / RB)^2 of
+// RB x RB pixels in row-major order inside the tile.
+struct BlockPos {
+    int view;
+    int x0, y0;      // block origin (view-local pixels)
+    int64_t tile;    // global tile id
+    bool valid;
+};
+
+FS_DEV BlockPos locate_block(int64_t b, int S, int RB, const fs_camera* cams, int num_views) {
+    // 32-bit arithmetic: launches keep b < 2^32; S and S / RB are powers of two
+    BlockPos bp;
+    const uint32_t bb = (uint32_t)b;
+    const int lsb = S / RB == 4 ? 2 : (S / RB == 2 ? 1 : 0);   // log2(S / RB)
+    const int ls = S == 32 ? 5 : (S == 16 ? 4 : 3);             // log2(S)
+    const uint32_t tile = bb >> (2 * lsb);
+    const uint32_t sub = bb & ((1u << (2 * lsb)) - 1u);
+    const int v = fs_view_of_tile(cams, num_views, tile);
+    const fs_camera& cam = cams[v];
+    const uint32_t tiles_x = ((uint32_t)cam.width + (uint32_t)S - 1u) >> ls;
+    const uint32_t local = tile - (uint32_t)cam.tile_offset;
+    const uint32_t ty = local / tiles_x, tx = local - ty * tiles_x;
+    bp.view = v;
+    bp.tile = tile;
+    bp.x0 = (int)(tx << ls) + (int)(sub & ((1u << lsb) - 1u)) * RB;
+    bp.y0 = (int)(ty << ls) + (int)(sub >> lsb) * RB;
+    bp.valid = bp.x0 < cam.width && bp.y0 < cam.height;
+    return bp;
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launch helpers implemented in the .hip files.
 // ---------------------------------------------------------------------------
@@ -483,6 +513,14 @@ struct FsWorkspace {
     uint32_t* render_offs;
     uint32_t* render_order;
     int64_t render_max_blocks;
+    // split Top-K render: (row slot, weight bits) of the first K blended
+    // surfels of every pixel, indexed [8x8 block][pixel of block][k]; the
+    // surfel index of every row slot of a block, [8x8 block][slot]; and the
+    // number of row slots of every block
+    uint2* topk_pairs;
+    uint32_t* topk_rows;
+    uint32_t* topk_nrows;
+    int64_t topk_pair_slots;
 };
 
 bool fs_workspace_layout(void* base, int64_t n, int32_t num_views, int64_t total_tiles, int64_t pair_capacity,
@@ -505,6 +543,17 @@ hipError_t fs_launch_render_forward(const FsRecord* records, const uint32_t* val
                                     int64_t total_tiles, const fs_opts& o, float* out_feat, float* out_T,
                                     int32_t* out_n, int32_t* out_last, int32_t* out_idx, uint64_t* counters,
                                     const FsWorkspace& ws, hipStream_t s);
+
+// Work order of render blocks (tile list length, longest first; ties in any
+// order) into ws.render_order; zeroes ws.render_ticket.
+hipError_t fs_launch_block_order(const uint32_t* ranges, int sb2, uint32_t nblocks, const FsWorkspace& ws,
+                                 hipStream_t s);
+
+hipError_t fs_launch_render_topk_split(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges,
+                                       const void* feats, int C, int64_t n, const fs_camera* cams, int num_views,
+                                       int64_t total_tiles, const fs_opts& o, float* out_feat, float* out_T,
+                                       int32_t* out_n, int32_t* out_last, int32_t* out_idx, uint64_t* counters,
+                                       const FsWorkspace& ws, hipStream_t s);
 
 hipError_t fs_launch_render_backward(const float* means, const float* scales, const float* quats,
                                      const float* opacity, const FsRecord* records, const uint32_t* vals,

@@ -42,31 +42,6 @@ FS_DEV uint32_t wave_or(uint32_t x) {
     return x;
 }
 
-struct BlockPos {
-    int view;
-    int x0, y0;      // block origin (view-local pixels)
-    int64_t tile;    // global tile id
-    bool valid;
-};
-
-FS_DEV BlockPos locate_block(int64_t b, int S, int RB, const fs_camera* cams, int num_views) {
-    BlockPos bp;
-    const int sb = S / RB;
-    const int64_t tile = b / (sb * sb);
-    const int sub = (int)(b % (sb * sb));
-    const int v = fs_view_of_tile(cams, num_views, tile);
-    const fs_camera& cam = cams[v];
-    const int tiles_x = (cam.width + S - 1) / S;
-    const int64_t local = tile - cam.tile_offset;
-    const int tx = (int)(local % tiles_x), ty = (int)(local / tiles_x);
-    bp.view = v;
-    bp.tile = tile;
-    bp.x0 = tx * S + (sub % sb) * RB;
-    bp.y0 = ty * S + (sub / sb) * RB;
-    bp.valid = bp.x0 < cam.width && bp.y0 < cam.height;
-    return bp;
-}
-
 // Bytes of a vector load of feature elements (16 B when C allows it).
 template <typename FT, bool VEC>
 struct RowVec {
@@ -130,24 +105,34 @@ FS_DEV void render_block(int64_t block, FwdShared<CPL, FT, WAVES, BG>& sm, const
     const float neg_half_log2e = -0.72134752044448170f;   // -log2(e) / 2
     uint32_t walked = 0, fetched = 0;
 
-    // record prefetch registers (the next batch is loaded while this one runs)
+    // Prefetch pipeline: the list values of batch b + 2 and the records of
+    // batch b + 1 are in flight while batch b is processed, so the dependent
+    // load (record address from list value) never stalls the walk.
     float4 pre[kRecSlots];
     uint32_t pre_rid[kRecSlots];
-    auto prefetch = [&](uint32_t b0) {
+    uint32_t nxt_rid[kRecSlots];
+    auto fetch_vals = [&](uint32_t b0, uint32_t* rid) {
 #pragma unroll
         for (int j = 0; j < kRecSlots; ++j) {
-            const int t = tid + j * NT;
-            const int e = t / kQ, q = t - e * kQ;
-            pre_rid[j] = 0xffffffffu;
-            pre[j] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (e < BG && b0 + (uint32_t)e < end) {
-                const uint32_t rid = vals[b0 + e];
-                pre_rid[j] = rid;
-                if ((int64_t)rid < num_records) pre[j] = reinterpret_cast<const float4*>(records + rid)[q];
-            }
+            const int e = (tid + j * NT) / kQ;
+            rid[j] = (e < BG && b0 + (uint32_t)e < end) ? vals[b0 + e] : 0xffffffffu;
         }
     };
-    if (start < end) prefetch(start);
+    auto fetch_records = [&](const uint32_t* rid) {
+#pragma unroll
+        for (int j = 0; j < kRecSlots; ++j) {
+            const int q = (tid + j * NT) % kQ;
+            pre_rid[j] = rid[j];
+            pre[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if ((int64_t)rid[j] < num_records) pre[j] = reinterpret_cast<const float4*>(records + rid[j])[q];
+        }
+    };
+    if (start < end) {
+        uint32_t r0[kRecSlots];
+        fetch_vals(start, r0);
+        fetch_records(r0);
+        fetch_vals(start + BG, nxt_rid);
+    }
 
     for (uint32_t b0 = start; b0 < end; b0 += BG) {
         const int nb = (int)(end - b0 < (uint32_t)BG ? end - b0 : (uint32_t)BG);
@@ -174,7 +159,10 @@ FS_DEV void render_block(int64_t block, FwdShared<CPL, FT, WAVES, BG>& sm, const
             }
         }
         __syncthreads();
-        if (b0 + BG < end) prefetch(b0 + BG);
+        if (b0 + BG < end) {
+            fetch_records(nxt_rid);
+            fetch_vals(b0 + 2 * BG, nxt_rid);
+        }
         // 2. weights, lanes = pixels
         uint32_t mask = 0u;
         if (!__all(done)) {
@@ -372,13 +360,28 @@ __global__ void order_scan_kernel(uint32_t* __restrict__ hist, uint32_t* __restr
     }
 }
 
+// Ranks are taken in LDS per workgroup; one global atomic per (workgroup,
+// bucket) reserves the workgroup's run of positions.
 __global__ void order_scatter_kernel(const uint32_t* __restrict__ ranges, int sb2, uint32_t nblocks,
                                      uint32_t* __restrict__ offs, uint32_t* __restrict__ order) {
+    __shared__ uint32_t cnt[64], base[64];
+    if (threadIdx.x < 64) cnt[threadIdx.x] = 0;
+    __syncthreads();
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nblocks) return;
-    const uint32_t t = b / sb2;
-    const uint32_t pos = atomicAdd(&offs[cost_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
-    if (pos < nblocks) order[pos] = b;
+    int k = 0;
+    uint32_t local = 0;
+    if (b < nblocks) {
+        const uint32_t t = b / sb2;
+        k = cost_bucket(ranges[2 * t + 1] - ranges[2 * t]);
+        local = atomicAdd(&cnt[k], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64 && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&offs[threadIdx.x], cnt[threadIdx.x]);
+    __syncthreads();
+    if (b < nblocks) {
+        const uint32_t pos = base[k] + local;
+        if (pos < nblocks) order[pos] = b;
+    }
 }
 
 __global__ void zero_u32_kernel(uint32_t* p, int count) {
@@ -404,18 +407,14 @@ hipError_t launch(const FsRecord* records, const uint32_t* vals, const uint32_t*
     constexpr int RB = WAVES == 1 ? 8 : 16;
     const int sb = o.tile / RB;
     const int64_t blocks = total_tiles * sb * sb;
+    if (blocks >= (int64_t(1) << 32)) return hipErrorInvalidValue;
     const int chunks = (C + 64 * CPL - 1) / (64 * CPL);
     const bool vec = (C % (16 / (int)sizeof(FT))) == 0;
     auto kern = vec ? render_fwd_kernel<CPL, FT, WAVES, BG, true> : render_fwd_kernel<CPL, FT, WAVES, BG, false>;
     if (o.schedule == FS_SCHED_PERSISTENT && chunks == 1 && blocks <= ws.render_max_blocks) {
         const uint32_t nb = (uint32_t)blocks;
-        const unsigned g = (unsigned)((nb + 255) / 256);
-        hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, ws.render_hist, 64);
-        hipLaunchKernelGGL(order_hist_kernel, dim3(g), dim3(256), 0, s, ranges, sb * sb, nb, ws.render_hist,
-                           ws.render_ticket);
-        hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, s, ws.render_hist, ws.render_offs);
-        hipLaunchKernelGGL(order_scatter_kernel, dim3(g), dim3(256), 0, s, ranges, sb * sb, nb, ws.render_offs,
-                           ws.render_order);
+        const hipError_t e = fs_launch_block_order(ranges, sb * sb, nb, ws, s);
+        if (e != hipSuccess) return e;
         int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), WAVES * 64, 0) !=
                 hipSuccess || per_cu < 1)
@@ -454,6 +453,20 @@ hipError_t launch_waves(const FsRecord* records, const uint32_t* vals, const uin
 }
 
 }  // namespace
+
+hipError_t fs_launch_block_order(const uint32_t* ranges, int sb2, uint32_t nblocks, const FsWorkspace& ws,
+                                 hipStream_t s) {
+    if (nblocks == 0) return hipSuccess;
+    if ((int64_t)nblocks > ws.render_max_blocks || ws.render_order == nullptr) return hipErrorInvalidValue;
+    const unsigned g = (nblocks + 255) / 256;
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, ws.render_hist, 64);
+    hipLaunchKernelGGL(order_hist_kernel, dim3(g), dim3(256), 0, s, ranges, sb2, nblocks, ws.render_hist,
+                       ws.render_ticket);
+    hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, s, ws.render_hist, ws.render_offs);
+    hipLaunchKernelGGL(order_scatter_kernel, dim3(g), dim3(256), 0, s, ranges, sb2, nblocks, ws.render_offs,
+                       ws.render_order);
+    return hipGetLastError();
+}
 
 hipError_t fs_launch_render_forward(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges,
                                     const void* feats, int C, int64_t n, const fs_camera* cams, int num_views,

@@ -1,0 +1,496 @@
+// render_topk.hip -- Top-K hard selection (Sec. 3.4) as two passes.
+//
+// Selection (lanes = pixels, one wave per 8x8 block): walks the block's
+// depth-sorted tile list front to back with exactly the per-pixel arithmetic
+// of the fused renderer (ray-splat response, alpha, transmittance, the T_stop
+// and K tests) and writes, for every pixel, the surfel index and blend weight
+// w = alpha T of each of its first K blended surfels to the workspace, plus
+// the final transmittance, blend count and optional index outputs.  It holds
+// no feature data, so it runs at high occupancy and hides the latency of its
+// dependent list -> record loads behind other waves.
+//
+// Gather (lanes = (pixel, 16-byte channel vector)): every thread reads its
+// pixel's (surfel, weight) list, issues the loads of all listed feature rows
+// before the first multiply-add, and accumulates w * c in list order with the
+// same fused multiply-adds as the fused renderer, so both schedules give the
+// same bits.  This pass is a stream: the feature image written (pixel-major,
+// C floats per pixel) dominates its traffic, and the rows it reads are shared
+// by neighbouring pixels and served mostly by L2.
+//
+// Both launches map workgroups to XCDs so that each XCD takes a contiguous
+// run of blocks (neighbouring tiles share surfels, so their records and rows
+// stay in that XCD's L2).
+#include "fs_internal.h"
+
+namespace {
+
+constexpr int kSelBatch = 32;   // list entries staged per step in the selection pass
+constexpr int kSub = 8;         // entries whose responses are evaluated together
+constexpr int kGatherThreads = 256;
+constexpr int kGatherUnroll = 8;  // (surfel, weight) pairs whose row loads are in flight together
+constexpr int kStagedK = 16;      // largest K of the staged gather (its lists live in LDS)
+
+// Workgroup -> work item: dispatch hands workgroup g to XCD g mod 8; remap so
+// that XCD x takes the contiguous run [x * per, (x + 1) * per).  The last
+// G mod 8 workgroups keep their own index.
+FS_DEV int64_t xcd_remap(int64_t g, int64_t G) {
+    const int64_t per = G / 8;
+    if (g >= per * 8) return g;
+    return (g % 8) * per + g / 8;
+}
+
+struct SelShared {
+    FsRecord rec[kSelBatch];
+    uint32_t recid[kSelBatch];
+    uint32_t sidx[kSelBatch];
+};
+
+__global__ void __launch_bounds__(64)
+topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restrict__ vals,
+                   const uint32_t* __restrict__ ranges, uint32_t n, int64_t num_records,
+                   const fs_camera* __restrict__ cams, int num_views, int S, fs_opts o, int64_t nblocks,
+                   const uint32_t* __restrict__ order, uint2* __restrict__ pairs, uint32_t* __restrict__ rows,
+                   uint32_t* __restrict__ nrows, float* __restrict__ out_T, int32_t* __restrict__ out_n,
+                   int32_t* __restrict__ out_last, int32_t* __restrict__ out_idx, uint64_t* __restrict__ counters) {
+    constexpr int BG = kSelBatch;
+    constexpr int kQ = FS_RECORD_BYTES / 16;          // float4 per record
+    constexpr int kRecSlots = (BG * kQ + 63) / 64;    // record float4 per lane
+    __shared__ SelShared sm;
+    const int lane = threadIdx.x;
+    // longest tile lists are dispatched first, so the longest walks overlap the rest
+    const int64_t block = order[blockIdx.x];
+    const BlockPos bp = locate_block(block, S, 8, cams, num_views);
+    if (!bp.valid) return;   // uniform across the wave
+    const fs_camera& cam = cams[bp.view];
+    const int px = bp.x0 + (lane & 7), py = bp.y0 + (lane >> 3);
+    const bool inside = px < cam.width && py < cam.height;
+    const int64_t pix = cam.pixel_offset + (int64_t)py * cam.width + px;
+    const uint32_t start = ranges[2 * bp.tile], end = ranges[2 * bp.tile + 1];
+    const int K = o.topk;
+    uint2* __restrict__ mine = pairs + (block * 64 + lane) * (int64_t)K;
+    uint32_t* __restrict__ rowlist = rows + block * 64 * (int64_t)K;
+
+    double T = 1.0;
+    int cnt = 0;
+    int last = -1;
+    bool done = !inside;
+    const double t_stop = o.t_stop;
+    const float neg_half_log2e = -0.72134752044448170f;   // -log2(e) / 2
+    uint32_t walked = 0;
+    uint32_t nslots = 0;   // rows of the block's row list so far
+
+    // list values of batch b + 2 and records of batch b + 1 are in flight
+    // while batch b is walked
+    float4 pre[kRecSlots];
+    uint32_t pre_rid[kRecSlots];
+    uint32_t nxt_rid[kRecSlots];
+    auto fetch_vals = [&](uint32_t b0, uint32_t* rid) {
+#pragma unroll
+        for (int j = 0; j < kRecSlots; ++j) {
+            const int e = (lane + j * 64) / kQ;
+            rid[j] = (e < BG && b0 + (uint32_t)e < end) ? vals[b0 + e] : 0xffffffffu;
+        }
+    };
+    auto fetch_records = [&](const uint32_t* rid) {
+#pragma unroll
+        for (int j = 0; j < kRecSlots; ++j) {
+            const int q = (lane + j * 64) % kQ;
+            pre_rid[j] = rid[j];
+            pre[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if ((int64_t)rid[j] < num_records) pre[j] = reinterpret_cast<const float4*>(records + rid[j])[q];
+        }
+    };
+    if (start < end) {
+        uint32_t r0[kRecSlots];
+        fetch_vals(start, r0);
+        fetch_records(r0);
+        fetch_vals(start + BG, nxt_rid);
+    }
+
+    for (uint32_t b0 = start; b0 < end; b0 += BG) {
+        const int nb = (int)(end - b0 < (uint32_t)BG ? end - b0 : (uint32_t)BG);
+        __syncthreads();   // the previous batch's records are no longer read
+#pragma unroll
+        for (int j = 0; j < kRecSlots; ++j) {
+            const int t = lane + j * 64;
+            const int e = t / kQ, q = t - e * kQ;
+            if (e < nb) {
+                float4 v4 = pre[j];
+                uint32_t rid = pre_rid[j];
+                if ((int64_t)rid >= num_records) {   // never happens for a well-formed list
+                    rid = 0u;
+                    v4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (q == 4) v4.w = __int_as_float((int)0xbff00000);   // k2 = -1: never accepted
+                    if (q == 5) v4.z = __int_as_float(1);                 // empty box
+                }
+                reinterpret_cast<float4*>(&sm.rec[e])[q] = v4;
+                if (q == 0) {
+                    sm.recid[e] = rid;
+                    sm.sidx[e] = rid % n;
+                }
+            }
+        }
+        __syncthreads();
+        if (b0 + BG < end) {
+            fetch_records(nxt_rid);
+            fetch_vals(b0 + 2 * BG, nxt_rid);
+        }
+        walked += (uint32_t)nb;
+        for (int e0 = 0; e0 < nb; e0 += kSub) {
+            // (a) responses of kSub entries: independent of each other and of
+            //     the transmittance, and computed without branches (box, stop
+            //     and accept tests become mask bits), so their FP64 chains and
+            //     LDS reads overlap
+            float al[kSub];
+            uint32_t hit = 0u;
+#pragma unroll
+            for (int u = 0; u < kSub; ++u) {
+                const int e = e0 + u < nb ? e0 + u : nb - 1;
+                const FsRecord r = sm.rec[e];   // whole record in registers: one basic block, no waits between fields
+                const bool box = (r.x1 >= bp.x0) & (r.x0 <= bp.x0 + 7) & (r.y1 >= bp.y0) & (r.y0 <= bp.y0 + 7);
+                const FsResp rs = fs_response(r, (double)(px - r.ax), (double)(py - r.ay));
+                const float G = __builtin_amdgcn_exp2f(neg_half_log2e * (float)rs.d2);
+                al[u] = fminf(o.alpha_max, r.o * G);
+                hit |= (uint32_t)(box & (e0 + u < nb) & (rs.d2 <= r.k2)) << u;
+            }
+            if (done) hit = 0u;
+            // (b) front-to-back transmittance over the accepted entries
+            float wv[kSub];
+            uint32_t bm = 0u;   // entries of this sub-batch the lane blends
+            const int c_start = cnt;
+#pragma unroll
+            for (int u = 0; u < kSub; ++u) {
+                wv[u] = 0.f;
+                if (((hit >> u) & 1u) && !done) {
+                    const double Tn = T * (1.0 - (double)al[u]);
+                    if (Tn < t_stop) {
+                        done = true;
+                    } else {
+                        wv[u] = (float)((double)al[u] * T);
+                        bm |= 1u << u;
+                        T = Tn;
+                        ++cnt;
+                        last = (int)(b0 + e0 + u);
+                        if (cnt == K) done = true;
+                    }
+                }
+            }
+            // (c) row slots: the entries any pixel of the block blends get
+            //     consecutive slots of the block's row list, in list order
+            uint32_t used = 0u;
+#pragma unroll
+            for (int u = 0; u < kSub; ++u) used |= (__ballot((bm >> u) & 1u) != 0ull ? 1u : 0u) << u;
+#pragma unroll
+            for (int u = 0; u < kSub; ++u) {
+                if ((bm >> u) & 1u) {
+                    const int j = c_start + __popc(bm & ((1u << u) - 1u));
+                    const uint32_t slot = nslots + (uint32_t)__popc(used & ((1u << u) - 1u));
+                    mine[j] = make_uint2(slot, __float_as_uint(wv[u]));
+                    if (out_idx) out_idx[pix * K + j] = (int32_t)sm.recid[e0 + u];
+                }
+            }
+            if (lane < kSub && ((used >> lane) & 1u))
+                rowlist[nslots + (uint32_t)__popc(used & ((1u << lane) - 1u))] = sm.sidx[e0 + lane];
+            nslots += (uint32_t)__popc(used);
+            if (__all(done)) break;
+        }
+        if (__all(done)) break;
+    }
+
+    if (counters != nullptr) {
+        int c = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) c += __shfl_xor(c, d, 64);
+        if (lane == 0) {
+            atomicAdd((unsigned long long*)&counters[0], (unsigned long long)walked);
+            atomicAdd((unsigned long long*)&counters[1], (unsigned long long)nslots);
+            atomicAdd((unsigned long long*)&counters[2], (unsigned long long)c);
+            atomicAdd((unsigned long long*)&counters[3], 1ull);
+        }
+    }
+    if (lane == 0) nrows[block] = nslots;
+    if (inside) {
+        out_T[pix] = (float)T;
+        out_n[pix] = cnt;
+        if (out_last) out_last[pix] = last;
+        if (out_idx)
+            for (int j = cnt; j < K; ++j) out_idx[pix * K + j] = -1;
+    }
+}
+
+// Feature vector of VE elements (16 bytes, or one element when C does not
+// allow aligned vectors) widened to float32.
+template <typename FT, int VE>
+struct Vec;
+template <>
+struct Vec<float, 4> {
+    using raw = float4;
+    FS_DEV static raw load(const float* p) { return *reinterpret_cast<const float4*>(p); }
+    FS_DEV static float at(const raw& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+};
+template <>
+struct Vec<float, 1> {
+    using raw = float;
+    FS_DEV static raw load(const float* p) { return *p; }
+    FS_DEV static float at(const raw& v, int) { return v; }
+};
+template <>
+struct Vec<uint16_t, 8> {
+    using raw = uint4;
+    FS_DEV static raw load(const uint16_t* p) { return *reinterpret_cast<const uint4*>(p); }
+    FS_DEV static float at(const raw& v, int i) {
+        const uint32_t w = i < 2 ? v.x : i < 4 ? v.y : i < 6 ? v.z : v.w;
+        return __uint_as_float((i & 1) ? (w & 0xffff0000u) : (w << 16));
+    }
+};
+template <>
+struct Vec<uint16_t, 1> {
+    using raw = uint16_t;
+    FS_DEV static raw load(const uint16_t* p) { return *p; }
+    FS_DEV static float at(const raw& v, int) { return __uint_as_float((uint32_t)v << 16); }
+};
+
+// Store VE accumulated channels at dst[c0 ...] (c0 + VE <= C for vectors).
+template <int VE>
+FS_DEV void store_vec(float* __restrict__ dst, int c0, const float* acc) {
+    if constexpr (VE == 4) {
+        *reinterpret_cast<float4*>(dst + c0) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    } else if constexpr (VE == 8) {
+        *reinterpret_cast<float4*>(dst + c0) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        *reinterpret_cast<float4*>(dst + c0 + 4) = make_float4(acc[4], acc[5], acc[6], acc[7]);
+    } else {
+        dst[c0] = acc[0];
+    }
+}
+
+// Gather, general form: TPP threads per pixel (a power of two, 4..64), each
+// taking channel vectors q, q + TPP, ... of its pixel and reading the pixel's
+// (slot, weight) list and the block's row list from memory.  A workgroup
+// covers 256 / TPP pixels of one 8x8 block.  Used when a pixel has more
+// channels or list slots than the staged form holds.
+template <typename FT, int VE, int TPP>
+__global__ void __launch_bounds__(kGatherThreads)
+topk_gather_general_kernel(const uint2* __restrict__ pairs, const int32_t* __restrict__ counts,
+                           const uint32_t* __restrict__ rows, const FT* __restrict__ feats, int C, int K,
+                           const fs_camera* __restrict__ cams, int num_views, int S, int64_t ngroups,
+                           float* __restrict__ out_feat) {
+    using V = Vec<FT, VE>;
+    constexpr int kPix = kGatherThreads / TPP;   // pixels per workgroup
+    constexpr int kGroups = 64 / kPix;           // workgroups per block
+    const int64_t g = xcd_remap(blockIdx.x, ngroups);
+    const int64_t block = g / kGroups;
+    const BlockPos bp = locate_block(block, S, 8, cams, num_views);
+    if (!bp.valid) return;
+    const fs_camera& cam = cams[bp.view];
+    const int p = (int)(g % kGroups) * kPix + (int)threadIdx.x / TPP;   // pixel of the block
+    const int q0 = (int)threadIdx.x % TPP;
+    const int px = bp.x0 + (p & 7), py = bp.y0 + (p >> 3);
+    if (px >= cam.width || py >= cam.height) return;
+    const int64_t pix = cam.pixel_offset + (int64_t)py * cam.width + px;
+    const int cnt = counts[pix];
+    const uint2* __restrict__ mine = pairs + (block * 64 + p) * (int64_t)K;
+    const uint32_t* __restrict__ rowlist = rows + block * 64 * (int64_t)K;
+    const int nv = (C + VE - 1) / VE;
+    float* __restrict__ dst = out_feat + pix * C;
+    for (int q = q0; q < nv; q += TPP) {
+        const int c0 = q * VE;
+        float acc[VE];
+#pragma unroll
+        for (int i = 0; i < VE; ++i) acc[i] = 0.f;
+        for (int j0 = 0; j0 < cnt; j0 += kGatherUnroll) {
+            uint2 pr[kGatherUnroll];
+#pragma unroll
+            for (int u = 0; u < kGatherUnroll; ++u)
+                if (j0 + u < cnt) pr[u] = mine[j0 + u];
+            uint32_t sidx[kGatherUnroll];
+#pragma unroll
+            for (int u = 0; u < kGatherUnroll; ++u)
+                if (j0 + u < cnt) sidx[u] = rowlist[pr[u].x];
+            typename V::raw row[kGatherUnroll];
+#pragma unroll
+            for (int u = 0; u < kGatherUnroll; ++u)
+                if (j0 + u < cnt) row[u] = V::load(feats + (int64_t)sidx[u] * C + c0);
+#pragma unroll
+            for (int u = 0; u < kGatherUnroll; ++u) {
+                if (j0 + u < cnt) {
+                    const float w = __uint_as_float(pr[u].y);
+#pragma unroll
+                    for (int i = 0; i < VE; ++i) acc[i] = fmaf(w, V::at(row[u], i), acc[i]);
+                }
+            }
+        }
+        store_vec<VE>(dst, c0, acc);
+    }
+}
+
+// Gather, staged form: one workgroup per 8x8 block.  The block's (slot,
+// weight) lists and counts go to LDS, then its feature rows are staged in
+// windows of W rows with direct global -> LDS loads (all of a window's loads
+// in flight together), and every pixel adds the rows of its list that fall
+// in the window, front to back.  TPP threads per pixel, each owning one
+// 16-byte channel vector of kPasses pixels of the block.
+template <typename FT, int TPP, int W>
+__global__ void __launch_bounds__(kGatherThreads)
+topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restrict__ counts,
+                       const uint32_t* __restrict__ rows, const uint32_t* __restrict__ nrows,
+                       const FT* __restrict__ feats, int C, int K, const fs_camera* __restrict__ cams, int num_views,
+                       int S, int64_t nblocks, float* __restrict__ out_feat) {
+    constexpr int VE = 16 / (int)sizeof(FT);
+    using V = Vec<FT, VE>;
+    constexpr int kPix = kGatherThreads / TPP;   // pixels per pass
+    constexpr int kPasses = 64 / kPix;           // pixels per thread
+    __shared__ __align__(16) uint4 s_rows[W * TPP];   // W rows of at most TPP vectors
+    __shared__ uint2 s_pairs[64 * kStagedK];
+    __shared__ int s_cnt[64];
+    __shared__ uint32_t s_rowid[W];
+    const int tid = (int)threadIdx.x;
+    const int64_t block = xcd_remap(blockIdx.x, nblocks);
+    const BlockPos bp = locate_block(block, S, 8, cams, num_views);
+    if (!bp.valid) return;   // uniform over the workgroup
+    const fs_camera& cam = cams[bp.view];
+    const int nv = C / VE;                       // vectors per row (C % VE == 0)
+    const int q = tid % TPP, sub = tid / TPP;
+    const bool has_vec = q < nv;
+    const uint32_t R = nrows[block];
+    const uint32_t* __restrict__ rowlist = rows + block * 64 * (int64_t)K;
+    // lists, counts and the first window's row ids: one round trip (a block
+    // no pixel of which blends anything has R = 0 and only writes zeros)
+    if (R > 0)
+        for (int t = tid; t < 64 * K; t += kGatherThreads) s_pairs[t] = pairs[block * 64 * (int64_t)K + t];
+    if (tid < 64 && R > 0) {
+        const int px = bp.x0 + (tid & 7), py = bp.y0 + (tid >> 3);
+        s_cnt[tid] = (px < cam.width && py < cam.height) ? counts[cam.pixel_offset + (int64_t)py * cam.width + px] : 0;
+    }
+    if (tid < W && (uint32_t)tid < R) s_rowid[tid] = rowlist[tid];
+    float acc[kPasses][VE];
+    int cur[kPasses];
+#pragma unroll
+    for (int k = 0; k < kPasses; ++k) {
+        cur[k] = 0;
+#pragma unroll
+        for (int i = 0; i < VE; ++i) acc[k][i] = 0.f;
+    }
+    __syncthreads();
+    for (uint32_t s0 = 0; s0 < R; s0 += W) {
+        const int nw = (int)(R - s0 < (uint32_t)W ? R - s0 : (uint32_t)W);
+        // stage rows [s0, s0 + nw): vector v of the window is row v / nv,
+        // column v % nv; lane l of an instruction lands at base + 16 l
+        const int nvec = nw * nv;
+        for (int i0 = (tid >> 6) * 64; i0 < nvec; i0 += kGatherThreads) {
+            const int v = i0 + (tid & 63);
+            if (v < nvec) {
+                const int r = v / nv, c = v - r * nv;
+                const FT* src = feats + (int64_t)s_rowid[r] * C + c * VE;
+                __builtin_amdgcn_global_load_lds((const void*)src,
+                                                 (__attribute__((address_space(3))) void*)&s_rows[i0], 16, 0, 0);
+            }
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        // accumulate: pairs of each pixel are in slot order
+#pragma unroll
+        for (int k = 0; k < kPasses; ++k) {
+            const int p = k * kPix + sub;
+            const int c = s_cnt[p];
+            int j = cur[k];
+            while (j < c) {
+                const uint2 pr = s_pairs[p * K + j];
+                if (pr.x >= s0 + (uint32_t)nw) break;
+                if (has_vec) {
+                    const typename V::raw f = *reinterpret_cast<const typename V::raw*>(
+                        reinterpret_cast<const unsigned char*>(s_rows) + ((pr.x - s0) * nv + q) * 16);
+                    const float w = __uint_as_float(pr.y);
+#pragma unroll
+                    for (int i = 0; i < VE; ++i) acc[k][i] = fmaf(w, V::at(f, i), acc[k][i]);
+                }
+                ++j;
+            }
+            cur[k] = j;
+        }
+        if (s0 + W < R) {
+            __syncthreads();   // the window is consumed
+            if (tid < W && s0 + W + (uint32_t)tid < R) s_rowid[tid] = rowlist[s0 + W + tid];
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kPasses; ++k) {
+        const int p = k * kPix + sub;
+        const int px = bp.x0 + (p & 7), py = bp.y0 + (p >> 3);
+        if (px < cam.width && py < cam.height && has_vec)
+            store_vec<VE>(out_feat + (cam.pixel_offset + (int64_t)py * cam.width + px) * C, q * VE, acc[k]);
+    }
+}
+
+template <typename FT, int VE>
+hipError_t launch_gather(const uint2* pairs, const int32_t* counts, const uint32_t* rows, const uint32_t* nrows,
+                         const void* feats, int C, int K, const fs_camera* cams, int num_views, int S,
+                         int64_t nblocks, float* out_feat, hipStream_t s) {
+    const int nv = (C + VE - 1) / VE;
+    const FT* f = static_cast<const FT*>(feats);
+    int tpp = 4;
+    while (tpp < nv && tpp < 64) tpp <<= 1;
+    if (VE > 1 && nv <= 64 && K <= kStagedK) {
+        if (nblocks >= (int64_t(1) << 32)) return hipErrorInvalidValue;
+#define FS_GATHER_LDS(TPP, W)                                                                                 \
+    hipLaunchKernelGGL((topk_gather_lds_kernel<FT, TPP, W>), dim3((unsigned)nblocks), dim3(kGatherThreads), 0, \
+                       s, pairs, counts, rows, nrows, f, C, K, cams, num_views, S, nblocks, out_feat)
+        // windows of about 24 KB of rows
+        switch (tpp) {
+            case 4: FS_GATHER_LDS(4, 64); break;
+            case 8: FS_GATHER_LDS(8, 64); break;
+            case 16: FS_GATHER_LDS(16, 64); break;
+            case 32: FS_GATHER_LDS(32, 48); break;
+            default: FS_GATHER_LDS(64, 24); break;
+        }
+#undef FS_GATHER_LDS
+        return hipGetLastError();
+    }
+    const int64_t groups = nblocks * 64 * tpp / kGatherThreads;
+    if (groups >= (int64_t(1) << 32)) return hipErrorInvalidValue;
+#define FS_GATHER(TPP)                                                                                            \
+    hipLaunchKernelGGL((topk_gather_general_kernel<FT, VE, TPP>), dim3((unsigned)groups), dim3(kGatherThreads), 0, \
+                       s, pairs, counts, rows, f, C, K, cams, num_views, S, groups, out_feat)
+    switch (tpp) {
+        case 4: FS_GATHER(4); break;
+        case 8: FS_GATHER(8); break;
+        case 16: FS_GATHER(16); break;
+        case 32: FS_GATHER(32); break;
+        default: FS_GATHER(64); break;
+    }
+#undef FS_GATHER
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t fs_launch_render_topk_split(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges,
+                                       const void* feats, int C, int64_t n, const fs_camera* cams, int num_views,
+                                       int64_t total_tiles, const fs_opts& o, float* out_feat, float* out_T,
+                                       int32_t* out_n, int32_t* out_last, int32_t* out_idx, uint64_t* counters,
+                                       const FsWorkspace& ws, hipStream_t s) {
+    if (total_tiles == 0) return hipSuccess;
+    const int sb = o.tile / 8;
+    const int64_t nblocks = total_tiles * sb * sb;
+    if (ws.topk_pairs == nullptr || ws.topk_rows == nullptr || ws.topk_nrows == nullptr ||
+        ws.topk_pair_slots < nblocks * 64 * (int64_t)o.topk ||
+        nblocks >= (int64_t(1) << 31))
+        return hipErrorInvalidValue;
+    hipError_t e = fs_launch_block_order(ranges, sb * sb, (uint32_t)nblocks, ws, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(topk_select_kernel, dim3((unsigned)nblocks), dim3(64), 0, s, records, vals, ranges,
+                       (uint32_t)n, n * num_views, cams, num_views, o.tile, o, nblocks, ws.render_order,
+                       ws.topk_pairs, ws.topk_rows, ws.topk_nrows, out_T, out_n, out_last, out_idx, counters);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const bool bf16 = o.feat_dtype == FS_FEAT_BF16;
+    if (bf16)
+        return C % 8 == 0 ? launch_gather<uint16_t, 8>(ws.topk_pairs, out_n, ws.topk_rows, ws.topk_nrows, feats, C,
+                                                       o.topk, cams, num_views, o.tile, nblocks, out_feat, s)
+                          : launch_gather<uint16_t, 1>(ws.topk_pairs, out_n, ws.topk_rows, ws.topk_nrows, feats, C,
+                                                       o.topk, cams, num_views, o.tile, nblocks, out_feat, s);
+    return C % 4 == 0 ? launch_gather<float, 4>(ws.topk_pairs, out_n, ws.topk_rows, ws.topk_nrows, feats, C, o.topk,
+                                                cams, num_views, o.tile, nblocks, out_feat, s)
+                      : launch_gather<float, 1>(ws.topk_pairs, out_n, ws.topk_rows, ws.topk_nrows, feats, C, o.topk,
+                                                cams, num_views, o.tile, nblocks, out_feat, s);
+}

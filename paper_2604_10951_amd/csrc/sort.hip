@@ -163,17 +163,29 @@ sort_pass_kernel(uint64_t* __restrict__ keys0, uint32_t* __restrict__ vals0, uin
             __hip_atomic_store(st + d, kPre | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             __hip_atomic_store(st + part * kRadix + d, kAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // look-back 8 predecessors per round trip (independent loads in flight)
             int64_t j = part - 1;
             while (true) {
-                const uint32_t s = __hip_atomic_load(st + j * kRadix + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t flag = s & ~kCnt;
-                if (flag == 0u) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
+                uint32_t sv[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    sv[k] = j - k >= 0 ? __hip_atomic_load(st + (j - k) * kRadix + d, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT)
+                                       : kPre;   // before partition 0: an empty inclusive prefix
+                int k = 0;
+                bool found = false;
+                for (; k < 8; ++k) {
+                    const uint32_t flag = sv[k] & ~kCnt;
+                    if (flag == 0u) break;
+                    excl += sv[k] & kCnt;
+                    if (flag == kPre) {
+                        found = true;
+                        break;
+                    }
                 }
-                excl += s & kCnt;
-                if (flag == kPre) break;
-                --j;
+                if (found) break;
+                j -= k;
+                if (k == 0) __builtin_amdgcn_s_sleep(1);
             }
             __hip_atomic_store(st + part * kRadix + d, kPre | (excl + total), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);

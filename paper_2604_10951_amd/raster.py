@@ -75,7 +75,7 @@ class Rasterizer:
         mode = {"precise": L.FS_TILES_PRECISE, "bbox": L.FS_TILES_BBOX}[tile_mode]
         dt = {"f32": L.FS_FEAT_F32, "bf16": L.FS_FEAT_BF16}[feat_dtype]
         self.feat_dtype = feat_dtype
-        sched = {"grid": L.FS_SCHED_GRID, "persistent": L.FS_SCHED_PERSISTENT}[schedule]
+        sched = {"grid": L.FS_SCHED_GRID, "persistent": L.FS_SCHED_PERSISTENT, "split": L.FS_SCHED_SPLIT}[schedule]
         self.opts = L.make_opts(tile, topk, mode, dt, alpha_min, alpha_max, t_stop, batch, sched)
         self.cam_arr, self.total_tiles, self.total_pixels = L.make_cameras(self.cams, tile)
         raw = bytes(ctypes.string_at(ctypes.addressof(self.cam_arr), ctypes.sizeof(self.cam_arr)))

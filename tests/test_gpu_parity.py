@@ -131,11 +131,12 @@ def test_small_full_blend(small, tile):
     check_image(fr, ref, rast, 0, scene.channels, 0, f"full tile={tile}")
 
 
-@pytest.mark.parametrize("K", [1, 2, 4, 8, 16])
-def test_small_topk(small, K):
+@pytest.mark.parametrize("K,schedule", [(1, "grid"), (2, "grid"), (4, "grid"), (8, "grid"), (16, "grid"),
+                                        (1, "split"), (4, "split"), (16, "split")])
+def test_small_topk(small, K, schedule):
     scene, cam = small
-    _print_case(f"small topk K={K}")
-    rast, fr = _render(scene, cam, tile=16, topk=K)
+    _print_case(f"small topk K={K} {schedule}")
+    rast, fr = _render(scene, cam, tile=16, topk=K, schedule=schedule)
     ref = oracle.render_scene(scene, cam, K=K)
     check_image(fr, ref, rast, 0, scene.channels, K, f"topk K={K}")
 
@@ -247,11 +248,11 @@ def headline():
     return scene, cam
 
 
-@pytest.mark.parametrize("K", [8, 0])
-def test_headline_sampled_pixels(headline, K):
+@pytest.mark.parametrize("K,schedule", [(8, "split"), (8, "grid"), (0, "grid")])
+def test_headline_sampled_pixels(headline, K, schedule):
     scene, cam = headline
-    _print_case(f"headline K={K}")
-    rast, fr = _render(scene, cam, tile=8, topk=K)     # the benchmark's launch configuration
+    _print_case(f"headline K={K} {schedule}")
+    rast, fr = _render(scene, cam, tile=8, topk=K, schedule=schedule)   # the benchmark's launch configurations
     n_pix = cam.width * cam.height
     rng = np.random.default_rng(11)
     nvec = fr.n.cpu().numpy()
