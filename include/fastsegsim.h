@@ -105,6 +105,11 @@ typedef struct fs_opts {
 
 enum { FS_SCHED_GRID = 0, FS_SCHED_PERSISTENT = 1, FS_SCHED_SPLIT = 2 };
 
+/* Per (view, surfel), fs_preprocess leaves FS_TILE_CACHE_WORDS uint32 for
+   fs_bin: the depth key and the first FS_INLINE_TILES tiles of the footprint. */
+#define FS_INLINE_TILES 3
+#define FS_TILE_CACHE_WORDS 4
+
 /* Size of the record fs_preprocess writes per (view, surfel). */
 #define FS_RECORD_BYTES 96
 /* Floats of per-record geometry gradient fs_render_backward accumulates. */
@@ -135,18 +140,25 @@ size_t fs_workspace_bytes(int64_t n, int32_t num_views, int64_t total_tiles, int
  * tile count (exact per-pixel footprint for FS_TILES_PRECISE).
  *   records        out, num_views * n * FS_RECORD_BYTES, record v*n+i
  *   tiles_touched  out, num_views * n uint32 (0 for culled surfels)
+ *   tile_cache     out, num_views * n * FS_TILE_CACHE_WORDS uint32 (16-byte
+ *                  aligned); for record r at [r * FS_TILE_CACHE_WORDS]: the
+ *                  depth key, then the first min(count, FS_INLINE_TILES)
+ *                  tiles of the footprint as view-local tx | ty << 16 (other
+ *                  slots unspecified)
  * cams_dev is a device array of num_views cameras laid out by fs_layout_views.
  */
 fs_status fs_preprocess(const float* means, const float* scales, const float* quats, const float* opacity, int64_t n,
                         const fs_camera* cams_dev, int32_t num_views, const fs_opts* opts, void* records,
-                        uint32_t* tiles_touched, hipStream_t stream);
+                        uint32_t* tiles_touched, uint32_t* tile_cache, hipStream_t stream);
 
 /*
  * fs_bin (Sec. 3.2).  Exclusive scan of tiles_touched over (view, surfel) in
- * record order, then every surfel re-derives its footprint from its
- * parameters (bit-identical to fs_preprocess) and writes, for each touched
- * tile, key = (global tile id << 32) | depth key and value = record index
- * v*n+i at its scanned offset.
+ * record order, then every record writes, for each touched tile, key =
+ * (global tile id << 32) | depth key and value = record index v*n+i at its
+ * scanned offset.  Depth keys and tiles come from tile_cache (fs_preprocess's
+ * output) when the footprint has at most FS_INLINE_TILES tiles; larger
+ * footprints are re-derived from the parameters (bit-identical to
+ * fs_preprocess).
  *   keys, vals       out, pair_capacity slots each
  *   num_pairs_dev    out, device int64: the pair count P (written even if it
  *                    exceeds pair_capacity; then keys beyond capacity are dropped)
@@ -155,17 +167,19 @@ fs_status fs_preprocess(const float* means, const float* scales, const float* qu
  */
 fs_status fs_bin(const float* means, const float* scales, const float* quats, const float* opacity, int64_t n,
                  const fs_camera* cams_dev, int32_t num_views, const fs_opts* opts, const uint32_t* tiles_touched,
-                 uint64_t* keys, uint32_t* vals, int64_t pair_capacity, int64_t* num_pairs_dev,
+                 const uint32_t* tile_cache, uint64_t* keys, uint32_t* vals, int64_t pair_capacity, int64_t* num_pairs_dev,
                  int64_t* num_pairs_host, void* workspace, hipStream_t stream);
 
 /*
- * fs_sort (Sec. 3.1: blending runs over depth-sorted surfels).  Stable LSD
- * radix sort (8-bit digits, single-pass "onesweep" passes) of the first P =
- * *num_pairs_dev pairs, by key, over 32 + ceil(log2 total_tiles) key bits;
- * equal keys keep emission order (surfel index order).  Result in place in
- * keys/vals.  tile_ranges (out, 2 * total_tiles uint32) receives [start, end)
- * of every tile's run (0, 0 if empty).  num_pairs_hint >= 0 is the host's
- * copy of P, used only to size the launch; pass -1 to size by capacity.
+ * fs_sort (Sec. 3.1: blending runs over depth-sorted surfels).  Orders the
+ * first P = min(*num_pairs_dev, pair_capacity) pairs by (key, value): by tile,
+ * then depth key, then record index -- the order a stable sort by key gives
+ * to fs_bin's emission order.  Result in place in keys/vals (counting sort by
+ * tile, then a sort of every tile's run).  tile_ranges (out, 2 * total_tiles
+ * uint32) receives [start, end) of every tile's run (start == end if empty).
+ * num_pairs_hint >= 0 is the host's copy of P, used only to size launches;
+ * pass -1 to size by capacity.  Keys whose tile is >= total_tiles are
+ * dropped (fs_bin never emits them).
  */
 fs_status fs_sort(uint64_t* keys, uint32_t* vals, int64_t pair_capacity, const int64_t* num_pairs_dev,
                   int64_t num_pairs_hint, int64_t total_tiles, uint32_t* tile_ranges, void* workspace,

@@ -17,6 +17,7 @@ FS_TILES_PRECISE, FS_TILES_BBOX = 0, 1
 FS_FEAT_F32, FS_FEAT_BF16 = 0, 1
 FS_SCHED_GRID, FS_SCHED_PERSISTENT, FS_SCHED_SPLIT = 0, 1, 2
 FS_RECORD_BYTES = 96
+FS_TILE_CACHE_WORDS = 4
 FS_GRAD_RECORD_FLOATS = 12
 
 
@@ -57,8 +58,8 @@ I32 = ctypes.c_int32
 SIGNATURES = {
     "fs_layout_views": ([ctypes.POINTER(FsCamera), I32, I32, ctypes.POINTER(I64), ctypes.POINTER(I64)], I32),
     "fs_workspace_bytes": ([I64, I32, I64, I64, ctypes.POINTER(FsOpts)], ctypes.c_size_t),
-    "fs_preprocess": ([P, P, P, P, I64, P, I32, ctypes.POINTER(FsOpts), P, P, P], I32),
-    "fs_bin": ([P, P, P, P, I64, P, I32, ctypes.POINTER(FsOpts), P, P, P, I64, P, ctypes.POINTER(I64), P, P], I32),
+    "fs_preprocess": ([P, P, P, P, I64, P, I32, ctypes.POINTER(FsOpts), P, P, P, P], I32),
+    "fs_bin": ([P, P, P, P, I64, P, I32, ctypes.POINTER(FsOpts), P, P, P, P, I64, P, ctypes.POINTER(I64), P, P], I32),
     "fs_sort": ([P, P, I64, P, I64, I64, P, P, P], I32),
     "fs_render_forward": ([P, P, P, P, I32, I64, P, I32, I64, ctypes.POINTER(FsOpts), P, P, P, P, P, P, P, P], I32),
     "fs_render_backward": ([P, P, P, P, P, P, P, P, I32, I64, P, I32, I64, ctypes.POINTER(FsOpts), P, P, P, P, P, P,

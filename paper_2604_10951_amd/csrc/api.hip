@@ -4,8 +4,7 @@
 
 #include "fs_internal.h"
 
-int fs_sort_passes(int64_t total_tiles);
-int64_t fs_sort_parts(int64_t capacity);
+int64_t fs_sort_scan_parts(int64_t total_tiles);
 
 namespace {
 
@@ -57,19 +56,18 @@ bool fs_workspace_layout(void* base, int64_t n, int32_t num_views, int64_t total
     w.scan_parts = (items + 1023) / 1024;
     w.scan_status = static_cast<uint64_t*>(take(sizeof(uint64_t) * (size_t)(w.scan_parts > 0 ? w.scan_parts : 1)));
     w.scan_ticket = static_cast<uint32_t*>(take(sizeof(uint32_t) * 16));
+    w.bin_over_sums = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)(w.scan_parts > 0 ? w.scan_parts : 1)));
+    w.bin_overflow = static_cast<uint2*>(take(sizeof(uint2) * (size_t)(items > 0 ? items : 1)));
     const size_t bin_bytes = align_up(off, 256);
     // sort stage
     off = 0;
-    w.npass = fs_sort_passes(total_tiles > 0 ? total_tiles : 1);
-    w.sort_parts = fs_sort_parts(pair_capacity);
-    w.hist = static_cast<uint32_t*>(take(sizeof(uint32_t) * 256 * w.npass));
-    w.digit_off = static_cast<uint32_t*>(take(sizeof(uint32_t) * 256 * w.npass));
-    w.sort_status = static_cast<uint32_t*>(
-        take(sizeof(uint32_t) * 256 * (size_t)w.npass * (size_t)(w.sort_parts > 0 ? w.sort_parts : 1)));
+    const int64_t tiles = total_tiles > 0 ? total_tiles : 1;
+    w.tile_cnt = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)tiles));
+    w.tile_fill = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)tiles));
+    w.sort_status = static_cast<uint64_t*>(take(sizeof(uint64_t) * (size_t)fs_sort_scan_parts(tiles)));
     w.sort_ticket = static_cast<uint32_t*>(take(sizeof(uint32_t) * 16));
-    w.sort_ctrl = static_cast<int32_t*>(take(sizeof(int32_t) * 16));
-    w.keys_alt = static_cast<uint64_t*>(take(sizeof(uint64_t) * (size_t)(pair_capacity > 0 ? pair_capacity : 1)));
-    w.vals_alt = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)(pair_capacity > 0 ? pair_capacity : 1)));
+    w.runs = static_cast<uint2*>(take(sizeof(uint2) * (size_t)(pair_capacity > 0 ? pair_capacity : 1)));
+    w.long_list = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)tiles));
     const size_t sort_bytes = align_up(off, 256);
     // render stage: work queue of render blocks (at most 16 per tile: 8x8 blocks of a 32x32 tile)
     off = 0;
@@ -123,27 +121,31 @@ size_t fs_workspace_bytes(int64_t n, int32_t num_views, int64_t total_tiles, int
 
 fs_status fs_preprocess(const float* means, const float* scales, const float* quats, const float* opacity, int64_t n,
                         const fs_camera* cams_dev, int32_t num_views, const fs_opts* opts, void* records,
-                        uint32_t* tiles_touched, hipStream_t stream) {
+                        uint32_t* tiles_touched, uint32_t* tile_cache, hipStream_t stream) {
     if (!valid_opts(opts) || n < 0 || num_views < 1 || !cams_dev) return FS_ERR_ARG;
-    if (n > 0 && (!means || !scales || !quats || !opacity || !records || !tiles_touched)) return FS_ERR_ARG;
+    if (n > 0 && (!means || !scales || !quats || !opacity || !records || !tiles_touched || !tile_cache))
+        return FS_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(tile_cache) % 16 != 0) return FS_ERR_ARG;
     if (n * (int64_t)num_views >= (int64_t(1) << 32)) return FS_ERR_ARG;
     return hip_status(fs_launch_preprocess(means, scales, quats, opacity, n, cams_dev, num_views, *opts,
-                                           static_cast<FsRecord*>(records), tiles_touched, stream));
+                                           static_cast<FsRecord*>(records), tiles_touched, tile_cache, stream));
 }
 
 fs_status fs_bin(const float* means, const float* scales, const float* quats, const float* opacity, int64_t n,
                  const fs_camera* cams_dev, int32_t num_views, const fs_opts* opts, const uint32_t* tiles_touched,
-                 uint64_t* keys, uint32_t* vals, int64_t pair_capacity, int64_t* num_pairs_dev,
+                 const uint32_t* tile_cache, uint64_t* keys, uint32_t* vals, int64_t pair_capacity, int64_t* num_pairs_dev,
                  int64_t* num_pairs_host, void* workspace, hipStream_t stream) {
     if (!valid_opts(opts) || n < 0 || num_views < 1 || !cams_dev || !num_pairs_dev || pair_capacity < 0)
         return FS_ERR_ARG;
-    if (n > 0 && (!means || !scales || !quats || !opacity || !tiles_touched || !workspace)) return FS_ERR_ARG;
+    if (n > 0 && (!means || !scales || !quats || !opacity || !tiles_touched || !tile_cache || !workspace))
+        return FS_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(tile_cache) % 16 != 0) return FS_ERR_ARG;
     if (pair_capacity > 0 && (!keys || !vals)) return FS_ERR_ARG;
     if (pair_capacity >= (int64_t(1) << 30)) return FS_ERR_ARG;
     FsWorkspace ws;
     if (!fs_workspace_layout(workspace, n, num_views, 1, pair_capacity, opts, &ws, nullptr)) return FS_ERR_ARG;
     fs_status st = hip_status(fs_launch_bin(means, scales, quats, opacity, n, cams_dev, num_views, *opts,
-                                            tiles_touched, keys, vals, pair_capacity, num_pairs_dev, ws, stream));
+                                            tiles_touched, tile_cache, keys, vals, pair_capacity, num_pairs_dev, ws, stream));
     if (st != FS_OK || !num_pairs_host) return st;
     int64_t p = 0;
     st = hip_status(hipMemcpyAsync(&p, num_pairs_dev, sizeof(int64_t), hipMemcpyDeviceToHost, stream));

@@ -2,13 +2,14 @@
 // one (tile, depth) key per touched tile (Sec. 3.2: every tile the precise
 // intersection assigns a surfel to gets one list entry).
 //
-// Single pass: each workgroup takes a partition of 1024 counts by atomic
-// ticket (so partitions are claimed in order and a workgroup only ever waits
-// on partitions that are already running), scans it with wave-level prefix
-// sums, resolves its global offset by decoupled look-back over the partition
-// status words, and then emits the keys of its surfels.  Emission re-derives
-// each footprint with the same double-precision code as preprocess, so the
-// emitted tiles are exactly the counted ones.
+// Two passes over the counts: the first writes the total of every partition
+// of 1024 counts; the second has every partition add up the totals before it
+// (no workgroup ever waits on another), scan its own counts with wave-level
+// prefix sums and emit its keys.  Emission takes the depth key and the tiles
+// fs_preprocess kept for footprints of at most FS_INLINE_TILES tiles; larger
+// footprints are queued and re-derived by a second kernel with the same
+// double-precision code preprocess counted them with, so the emitted tiles
+// are exactly the counted ones.
 #include "fs_internal.h"
 
 namespace {
@@ -16,17 +17,8 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kItems = 4;                       // counts per lane
 constexpr int kPart = kThreads * kItems;        // counts per partition
-constexpr uint64_t kFlagAgg = 1ull << 62;       // partition aggregate available
-constexpr uint64_t kFlagPre = 2ull << 62;       // inclusive prefix available
-constexpr uint64_t kValMask = (1ull << 62) - 1;
 
 __global__ void zero_count_kernel(int64_t* p) { *p = 0; }
-
-__global__ void clear_u64_kernel(uint64_t* p, int64_t count, uint32_t* ticket) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = 0;
-    if (i == 0) *ticket = 0;
-}
 
 FS_DEV uint32_t wave_inclusive_scan(uint32_t x) {
     const int lane = threadIdx.x & 63;
@@ -38,20 +30,77 @@ FS_DEV uint32_t wave_inclusive_scan(uint32_t x) {
     return x;
 }
 
+// Pass 1 of the scan: the total count of every partition of kPart counts and
+// its number of footprints too large for the inline tiles.
+__global__ void __launch_bounds__(kThreads)
+bin_sums_kernel(const uint32_t* __restrict__ counts, int64_t items, uint64_t* __restrict__ sums,
+                uint32_t* __restrict__ over_sums) {
+    __shared__ uint64_t s_wave[kThreads / 64];
+    __shared__ uint32_t s_over[kThreads / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t base = (int64_t)blockIdx.x * kPart + (int64_t)tid * kItems;
+    uint64_t sum = 0;
+    uint32_t over = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+        const uint32_t c = (base + j < items) ? counts[base + j] : 0u;
+        sum += c;
+        over += c > FS_INLINE_TILES ? 1u : 0u;
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        sum += __shfl_xor(sum, d, 64);
+        over += __shfl_xor(over, d, 64);
+    }
+    if (lane == 0) {
+        s_wave[wave] = sum;
+        s_over[wave] = over;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t t = 0;
+        uint32_t v = 0;
+        for (int w = 0; w < kThreads / 64; ++w) {
+            t += s_wave[w];
+            v += s_over[w];
+        }
+        sums[blockIdx.x] = t;
+        over_sums[blockIdx.x] = v;
+    }
+}
+
+// Pass 2: every partition adds up the totals before it (in parallel, no
+// inter-workgroup waiting), scans its counts and emits its pairs.
 __global__ void __launch_bounds__(kThreads)
 bin_kernel(const float* __restrict__ means, const float* __restrict__ scales, const float* __restrict__ quats,
            const float* __restrict__ opacity, int64_t n, const fs_camera* __restrict__ cams, fs_opts o,
-           const uint32_t* __restrict__ counts, int64_t items, uint64_t* __restrict__ keys,
+           const uint32_t* __restrict__ counts, const uint4* __restrict__ tile_cache, int64_t items,
+           uint2* __restrict__ overflow, uint64_t* __restrict__ keys,
            uint32_t* __restrict__ vals, int64_t capacity, int64_t* __restrict__ num_pairs,
-           uint64_t* __restrict__ status, uint32_t* __restrict__ ticket, int64_t parts) {
-    __shared__ uint32_t s_part;
+           const uint64_t* __restrict__ sums, const uint32_t* __restrict__ over_sums,
+           uint32_t* __restrict__ over_total, int64_t parts) {
     __shared__ uint64_t s_wave[kThreads / 64];
-    __shared__ uint64_t s_prefix;
+    __shared__ uint64_t s_pre[kThreads / 64];
+    __shared__ uint32_t s_over[kThreads / 64];
+    __shared__ uint32_t s_over_pre[kThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) s_part = atomicAdd(ticket, 1u);
-    __syncthreads();
-    const int64_t part = s_part;
-    if (part >= parts) return;
+    const int64_t part = blockIdx.x;
+    // prefixes: totals of partitions [0, part)
+    uint64_t pre = 0;
+    uint32_t opre = 0;
+    for (int64_t k = tid; k < part; k += kThreads) {
+        pre += sums[k];
+        opre += over_sums[k];
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        pre += __shfl_xor(pre, d, 64);
+        opre += __shfl_xor(opre, d, 64);
+    }
+    if (lane == 0) {
+        s_pre[wave] = pre;
+        s_over_pre[wave] = opre;
+    }
     const int64_t base = part * kPart + (int64_t)tid * kItems;
     uint32_t c[kItems];
     uint32_t sum = 0;
@@ -64,72 +113,89 @@ bin_kernel(const float* __restrict__ means, const float* __restrict__ scales, co
     const uint32_t incl = wave_inclusive_scan(sum);
     if (lane == 63) s_wave[wave] = incl;
     __syncthreads();
-    uint64_t wave_excl = 0, total = 0;
+    uint64_t wave_excl = 0, total = 0, prefix = 0;
+    uint32_t over_prefix = 0;
     for (int w = 0; w < kThreads / 64; ++w) {
         if (w < wave) wave_excl += s_wave[w];
         total += s_wave[w];
+        prefix += s_pre[w];
+        over_prefix += s_over_pre[w];
     }
-    if (wave == 0) {
-        // decoupled look-back, one wave: lane l reads the status of partition
-        // j - l, so each round trip covers 64 predecessors
-        uint64_t prefix = 0;
-        if (part == 0) {
-            if (lane == 0)
-                __hip_atomic_store(status + part, kFlagPre | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            if (lane == 0)
-                __hip_atomic_store(status + part, kFlagAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            int64_t j = part - 1;
-            while (true) {
-                const int64_t idx = j - lane;
-                const uint64_t st = idx >= 0 ? __hip_atomic_load(status + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                             : kFlagPre;   // before partition 0: an empty inclusive prefix
-                const uint64_t flag = st & ~kValMask;
-                const uint64_t notready = __ballot(flag == 0);
-                const uint64_t pre = __ballot(flag == kFlagPre);
-                const int limit = notready ? __builtin_ctzll(notready) : 64;
-                const int first_pre = pre ? __builtin_ctzll(pre) : 64;
-                const bool found = first_pre < limit;
-                const int take = found ? first_pre + 1 : limit;     // lanes [0, take) are summed
-                uint64_t v = lane < take ? (st & kValMask) : 0ull;
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) v += __shfl_xor(v, d, 64);
-                prefix += v;
-                if (found) break;
-                j -= take;
-                if (take == 0) __builtin_amdgcn_s_sleep(1);
-            }
-            if (lane == 0)
-                __hip_atomic_store(status + part, kFlagPre | (prefix + total), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (lane == 0) {
-            s_prefix = prefix;
-            if (part == parts - 1) *num_pairs = (int64_t)(prefix + total);
-        }
+    if (tid == 0 && part == parts - 1) {
+        *num_pairs = (int64_t)(prefix + total);
+        *over_total = over_prefix + over_sums[part];
     }
-    __syncthreads();
-    uint64_t off = s_prefix + wave_excl + (incl - sum);
-    // emission
+    uint64_t off = prefix + wave_excl + (incl - sum);
+    // emission: footprints of at most FS_INLINE_TILES tiles from the ids
+    // fs_preprocess kept; larger ones go to the overflow list
     const int S = o.tile;
+    // overflow slots in record order: partition prefix, then wave and lane
+    uint32_t nover = 0;
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) nover += c[j] > FS_INLINE_TILES ? 1u : 0u;
+    uint32_t over_incl = nover;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(over_incl, d, 64);
+        if (lane >= d) over_incl += y;
+    }
+    if (lane == 63) s_over[wave] = over_incl;
+    __syncthreads();
+    uint32_t over_slot = over_prefix + over_incl - nover;
+    for (int w = 0; w < wave; ++w) over_slot += s_over[w];
 #pragma unroll 1
     for (int j = 0; j < kItems; ++j) {
         const int64_t r = base + j;
-        if (c[j] == 0) continue;
+        const uint64_t o0 = off;
+        off += c[j];
+        if (c[j] > FS_INLINE_TILES) {
+            overflow[over_slot++] = make_uint2((uint32_t)r, (uint32_t)(o0 < (uint64_t)capacity ? o0 : capacity));
+            continue;
+        }
+        if (c[j] == 0 || o0 >= (uint64_t)capacity) continue;
+        const int v = (int)(r / n);
+        const fs_camera& cam = cams[v];
+        const uint32_t tiles_x = ((uint32_t)cam.width + (uint32_t)S - 1u) / (uint32_t)S;
+        const uint4 cache = tile_cache[r];
+        const uint32_t id[FS_INLINE_TILES] = {cache.y, cache.z, cache.w};
+        const uint64_t zk = cache.x;
+#pragma unroll
+        for (int k = 0; k < FS_INLINE_TILES; ++k) {
+            if ((uint32_t)k < c[j] && o0 + k < (uint64_t)capacity) {
+                const uint64_t t = (uint64_t)cam.tile_offset + (uint64_t)(id[k] >> 16) * tiles_x + (id[k] & 0xffffu);
+                keys[o0 + k] = (t << 32) | zk;
+                vals[o0 + k] = (uint32_t)r;
+            }
+        }
+    }
+}
+
+// Footprints with more tiles than the inline ids hold: one lane per record,
+// re-derived from the parameters with the code fs_preprocess counted them with.
+__global__ void __launch_bounds__(kThreads)
+bin_overflow_kernel(const float* __restrict__ means, const float* __restrict__ scales,
+                    const float* __restrict__ quats, const float* __restrict__ opacity, int64_t n,
+                    const fs_camera* __restrict__ cams, fs_opts o, const uint32_t* __restrict__ counts,
+                    const uint2* __restrict__ overflow, const uint32_t* __restrict__ ticket,
+                    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, int64_t capacity) {
+    const uint32_t total = ticket[1];
+    const int S = o.tile;
+    for (uint32_t k = blockIdx.x * kThreads + threadIdx.x; k < total; k += gridDim.x * kThreads) {
+        const uint2 e = overflow[k];
+        const int64_t r = e.x;
         const int v = (int)(r / n);
         const int64_t i = r - (int64_t)v * n;
         const fs_camera& cam = cams[v];
         const int tiles_x = (cam.width + S - 1) / S;
         FsGeo g;
         FsFootprint fp;
-        uint64_t o0 = off;
-        off += c[j];
         if (!fs_project(means + 3 * i, scales + 2 * i, quats + 4 * i, opacity[i], cam, (double)o.alpha_min, g))
             continue;
         if (!fs_footprint(g, cam.width, cam.height, fp)) continue;
         const uint64_t zk = g.zkey;
         const int64_t toff = cam.tile_offset;
-        uint64_t end = o0 + c[j];
+        uint64_t o0 = e.y;
+        const uint64_t end = o0 + counts[r];
         auto emit = [&](int tx, int ty) {
             if (o0 < end && o0 < (uint64_t)capacity) {
                 keys[o0] = ((uint64_t)(toff + (int64_t)ty * tiles_x + tx) << 32) | zk;
@@ -152,17 +218,23 @@ bin_kernel(const float* __restrict__ means, const float* __restrict__ scales, co
 
 hipError_t fs_launch_bin(const float* means, const float* scales, const float* quats, const float* opacity, int64_t n,
                          const fs_camera* cams, int32_t num_views, const fs_opts& o, const uint32_t* tiles_touched,
-                         uint64_t* keys, uint32_t* vals, int64_t capacity, int64_t* num_pairs, const FsWorkspace& ws,
-                         hipStream_t s) {
+                         const uint32_t* tile_cache, uint64_t* keys, uint32_t* vals, int64_t capacity,
+                         int64_t* num_pairs, const FsWorkspace& ws, hipStream_t s) {
     const int64_t items = n * (int64_t)num_views;
     const int64_t parts = (items + kPart - 1) / kPart;
     if (parts == 0) {
         hipLaunchKernelGGL(zero_count_kernel, dim3(1), dim3(1), 0, s, num_pairs);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(clear_u64_kernel, dim3((unsigned)((parts + 255) / 256)), dim3(256), 0, s, ws.scan_status, parts,
-                       ws.scan_ticket);
+    hipLaunchKernelGGL(bin_sums_kernel, dim3((unsigned)parts), dim3(kThreads), 0, s, tiles_touched, items,
+                       ws.scan_status, ws.bin_over_sums);
     hipLaunchKernelGGL(bin_kernel, dim3((unsigned)parts), dim3(kThreads), 0, s, means, scales, quats, opacity, n, cams, o,
-                       tiles_touched, items, keys, vals, capacity, num_pairs, ws.scan_status, ws.scan_ticket, parts);
+                       tiles_touched, reinterpret_cast<const uint4*>(tile_cache), items, ws.bin_overflow, keys, vals,
+                       capacity, num_pairs, ws.scan_status, ws.bin_over_sums, ws.scan_ticket + 1, parts);
+    // overflow records: a grid of about one lane per 16 records, each lane striding
+    const int64_t ob = (items / 16 + kThreads - 1) / kThreads;
+    const unsigned oblocks = (unsigned)(ob < 1 ? 1 : (ob > 4096 ? 4096 : ob));
+    hipLaunchKernelGGL(bin_overflow_kernel, dim3(oblocks), dim3(kThreads), 0, s, means, scales, quats, opacity, n, cams,
+                       o, tiles_touched, ws.bin_overflow, ws.scan_ticket, keys, vals, capacity);
     return hipGetLastError();
 }

@@ -494,19 +494,18 @@ FS_DEV BlockPos locate_block(int64_t b, int S, int RB, const fs_camera* cams, in
 // ---------------------------------------------------------------------------
 struct FsWorkspace {
     // bin (scan + emit)
-    uint64_t* scan_status;
-    uint32_t* scan_ticket;
+    uint64_t* scan_status;   // partition totals
+    uint32_t* bin_over_sums; // per partition: footprints with more than FS_INLINE_TILES tiles
+    uint32_t* scan_ticket;   // [1]: overflow count
     int64_t scan_parts;
+    uint2* bin_overflow;     // (record, first offset) of footprints with more than FS_INLINE_TILES tiles
     // sort
-    uint32_t* hist;          // npass x 256
-    uint32_t* digit_off;     // npass x 256
-    uint32_t* sort_status;   // npass x parts x 256
-    uint32_t* sort_ticket;   // npass
-    int32_t* sort_ctrl;      // [0..npass): source buffer of each pass (-1: skipped); [npass]: final buffer
-    uint64_t* keys_alt;
-    uint32_t* vals_alt;
-    int64_t sort_parts;
-    int npass;
+    uint32_t* tile_cnt;      // pairs per tile
+    uint32_t* tile_fill;     // scatter cursor per tile
+    uint64_t* sort_status;   // look-back status of the tile-count scan partitions
+    uint32_t* sort_ticket;
+    uint2* runs;             // pairs grouped by tile, (depth key, record), capacity entries
+    uint32_t* long_list;     // tiles whose runs are longer than one wave sorts
     // render
     uint32_t* render_ticket;
     uint32_t* render_hist;
@@ -528,12 +527,12 @@ bool fs_workspace_layout(void* base, int64_t n, int32_t num_views, int64_t total
 
 hipError_t fs_launch_preprocess(const float* means, const float* scales, const float* quats, const float* opacity,
                                 int64_t n, const fs_camera* cams, int32_t num_views, const fs_opts& o,
-                                FsRecord* records, uint32_t* tiles_touched, hipStream_t s);
+                                FsRecord* records, uint32_t* tiles_touched, uint32_t* tile_cache, hipStream_t s);
 
 hipError_t fs_launch_bin(const float* means, const float* scales, const float* quats, const float* opacity, int64_t n,
                          const fs_camera* cams, int32_t num_views, const fs_opts& o, const uint32_t* tiles_touched,
-                         uint64_t* keys, uint32_t* vals, int64_t capacity, int64_t* num_pairs, const FsWorkspace& ws,
-                         hipStream_t s);
+                         const uint32_t* tile_cache, uint64_t* keys, uint32_t* vals, int64_t capacity,
+                         int64_t* num_pairs, const FsWorkspace& ws, hipStream_t s);
 
 hipError_t fs_launch_sort(uint64_t* keys, uint32_t* vals, int64_t capacity, const int64_t* num_pairs, int64_t hint,
                           int64_t total_tiles, uint32_t* ranges, const FsWorkspace& ws, hipStream_t s);

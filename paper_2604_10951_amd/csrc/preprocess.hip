@@ -6,6 +6,8 @@
 // tile count is the exact per-pixel footprint count.
 #include "fs_internal.h"
 
+static_assert(FS_INLINE_TILES == 3 && FS_TILE_CACHE_WORDS == 4, "the cache is one uint4 per record");
+
 namespace {
 
 constexpr int kThreads = 256;
@@ -13,7 +15,7 @@ constexpr int kThreads = 256;
 __global__ void __launch_bounds__(kThreads)
 preprocess_kernel(const float* __restrict__ means, const float* __restrict__ scales, const float* __restrict__ quats,
                   const float* __restrict__ opacity, int64_t n, const fs_camera* __restrict__ cams, fs_opts o,
-                  FsRecord* __restrict__ records, uint32_t* __restrict__ tiles_touched) {
+                  FsRecord* __restrict__ records, uint32_t* __restrict__ tiles_touched, uint4* __restrict__ tile_cache) {
     const int v = blockIdx.y;
     const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
@@ -31,6 +33,13 @@ preprocess_kernel(const float* __restrict__ means, const float* __restrict__ sca
     rec.y0 = 1;
     rec.y1 = 0;
     uint32_t count = 0;
+    uint32_t ids[FS_INLINE_TILES] = {0u, 0u, 0u};   // first tiles of the footprint, tx | ty << 16
+    auto note = [&](int tx, int ty) {
+#pragma unroll
+        for (int k = 0; k < FS_INLINE_TILES; ++k)
+            if (count == (uint32_t)k) ids[k] = (uint32_t)tx | ((uint32_t)ty << 16);
+        ++count;
+    };
     FsGeo g;
     const float op = opacity[i];
     if (fs_project(means + 3 * i, scales + 2 * i, quats + 4 * i, op, cam, (double)o.alpha_min, g)) {
@@ -39,10 +48,17 @@ preprocess_kernel(const float* __restrict__ means, const float* __restrict__ sca
             const int S = o.tile;
             if (o.tile_mode == FS_TILES_BBOX) {
                 int tx0, tx1, ty0, ty1;
-                if (fs_bbox_tiles(fp, cam.width, cam.height, S, tx0, tx1, ty0, ty1))
-                    count = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+                if (fs_bbox_tiles(fp, cam.width, cam.height, S, tx0, tx1, ty0, ty1)) {
+                    const uint32_t nt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+                    if (nt <= FS_INLINE_TILES) {
+                        for (int ty = ty0; ty <= ty1; ++ty)
+                            for (int tx = tx0; tx <= tx1; ++tx) note(tx, ty);
+                    } else {
+                        count = nt;
+                    }
+                }
             } else {
-                fs_sweep_tiles(fp, S, [&](int, int) { ++count; });
+                fs_sweep_tiles(fp, S, note);
             }
         }
         if (count > 0) {
@@ -73,16 +89,17 @@ preprocess_kernel(const float* __restrict__ means, const float* __restrict__ sca
     }
     records[r] = rec;
     tiles_touched[r] = count;
+    tile_cache[r] = make_uint4(g.zkey, ids[0], ids[1], ids[2]);
 }
 
 }  // namespace
 
 hipError_t fs_launch_preprocess(const float* means, const float* scales, const float* quats, const float* opacity,
                                 int64_t n, const fs_camera* cams, int32_t num_views, const fs_opts& o,
-                                FsRecord* records, uint32_t* tiles_touched, hipStream_t s) {
+                                FsRecord* records, uint32_t* tiles_touched, uint32_t* tile_cache, hipStream_t s) {
     if (n == 0) return hipSuccess;
     dim3 grid((unsigned)((n + kThreads - 1) / kThreads), (unsigned)num_views);
     hipLaunchKernelGGL(preprocess_kernel, grid, dim3(kThreads), 0, s, means, scales, quats, opacity, n, cams, o,
-                       records, tiles_touched);
+                       records, tiles_touched, reinterpret_cast<uint4*>(tile_cache));
     return hipGetLastError();
 }

@@ -1,280 +1,448 @@
-// sort.hip -- stable LSD radix sort of (tile << 32 | depth-key, record) pairs
-// and per-tile ranges (surfels are blended depth-sorted, Sec. 3.1; the
+// sort.hip -- per-tile depth ordering of the (tile << 32 | depth-key, record)
+// pairs and per-tile ranges (surfels are blended depth-sorted, Sec. 3.1; the
 // pipeline is tile based, Sec. 3.2).
 //
-// Structure ("onesweep"): one kernel builds the 256-bucket histograms of every
-// 8-bit digit in a single read of the keys; a one-workgroup kernel scans them
-// into per-pass digit offsets and marks passes whose digit is the same for
-// every key (those are identity permutations and are skipped on the device,
-// which keeps graph capture free of host decisions); then one kernel per pass
-// ranks and scatters.  A pass kernel takes 4096-key partitions by atomic
-// ticket, ranks keys inside each wave64 with ballot-based digit matching
-// (stable: keys are visited in index order), combines the four waves in LDS,
-// and resolves the partition's global position per digit by decoupled
-// look-back over 32-bit status words (2 flag bits + 30-bit count).
+// The required order is (tile, depth key, record): the order a stable sort on
+// the 64-bit key gives, since a record is emitted at most once per tile and
+// records are emitted in increasing order.  It is produced in two steps that
+// suit a list split into many short per-tile runs:
+//   1. a counting sort by tile: per-tile counts (LDS histograms per chunk of
+//      pairs), one exclusive scan that also yields every tile's [start, end)
+//      range, and a scatter that places each pair at its tile's start plus a
+//      cursor (any order inside the tile);
+//   2. a sort of every tile's run by (depth key, record), as 64-bit composite
+//      keys: runs of up to kWaveCap entries by one wave each (bitonic network
+//      in the wave's LDS slice), up to kLargeCap by a workgroup (bitonic in
+//      64 KB of LDS), longer runs by a stable one-workgroup LSD radix sort
+//      through global memory.
+// Every launch is sized from the capacity, not from the device-side pair
+// count, so the sequence can be captured in a graph.
 #include "fs_internal.h"
 
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kItems = 16;
-constexpr int kPart = kThreads * kItems;   // 4096 keys per partition
-constexpr int kRadix = 256;
-constexpr uint32_t kAgg = 1u << 30;
-constexpr uint32_t kPre = 2u << 30;
-constexpr uint32_t kCnt = (1u << 30) - 1u;
-constexpr int kMaxPass = 8;
-
-__global__ void sort_clear_kernel(uint32_t* hist, int64_t nhist, uint32_t* status, int64_t nstatus, uint32_t* tickets,
-                                  int npass, uint32_t* ranges, int64_t nranges) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nstatus; i += stride) status[i] = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nranges; i += stride) ranges[i] = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nhist; i += stride) hist[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x < npass) tickets[threadIdx.x] = 0;
-}
+constexpr int kWaveCap = 256;     // entries per run sorted by one wave (2 KB of LDS per wave)
+constexpr int kLargeCap = 8192;   // entries per run sorted in LDS by a workgroup (64 KB)
+constexpr int kLdsTiles = 16384;  // tile counts kept in LDS by the count and scatter kernels
+constexpr int kChunk = 2048;      // pairs per workgroup in the count and scatter kernels
+constexpr int kLongGrid = 512;    // workgroups working through the long-run list
+constexpr int kLongThreads = 1024;
+constexpr int kScanItems = 4;
+constexpr int kScanPart = kThreads * kScanItems;
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagPre = 2ull << 62;
+constexpr uint64_t kValMask = (1ull << 62) - 1;
 
 FS_DEV int64_t load_count(const int64_t* num_pairs, int64_t capacity) {
-    int64_t p = *num_pairs;
+    const int64_t p = *num_pairs;
     return p < capacity ? p : capacity;
 }
 
-__global__ void __launch_bounds__(kThreads)
-sort_hist_kernel(const uint64_t* __restrict__ keys, const int64_t* __restrict__ num_pairs, int64_t capacity,
-                 int npass, uint32_t* __restrict__ hist) {
-    __shared__ uint32_t h[kMaxPass * kRadix];
-    for (int i = threadIdx.x; i < npass * kRadix; i += kThreads) h[i] = 0;
-    __syncthreads();
-    const int64_t P = load_count(num_pairs, capacity);
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < P; i += stride) {
-        const uint64_t k = keys[i];
-        for (int p = 0; p < npass; ++p) atomicAdd(&h[p * kRadix + ((k >> (8 * p)) & 0xff)], 1u);
+__global__ void sort_clear_kernel(uint32_t* __restrict__ cnt, uint32_t* __restrict__ fill, int64_t tiles,
+                                  uint64_t* __restrict__ status, int64_t parts, uint32_t* __restrict__ ticket) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tiles; i += stride) {
+        cnt[i] = 0;
+        fill[i] = 0;
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < npass * kRadix; i += kThreads)
-        if (h[i]) atomicAdd(&hist[i], h[i]);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < parts; i += stride) status[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 2) ticket[threadIdx.x] = 0;   // scan ticket, long-run count
 }
 
+// Per-tile counts.  With at most kLdsTiles tiles every workgroup counts a
+// contiguous chunk of pairs in an LDS histogram and adds its non-zero bins to
+// the global counts, so a tile with many pairs costs one global atomic per
+// workgroup, not one per pair; with more tiles, pairs are counted with
+// global atomics.
 __global__ void __launch_bounds__(kThreads)
-sort_scan_kernel(const uint32_t* __restrict__ hist, const int64_t* __restrict__ num_pairs, int64_t capacity,
-                 int npass, uint32_t* __restrict__ digit_off, int32_t* __restrict__ ctrl) {
-    __shared__ uint32_t s[kRadix];
-    __shared__ int trivial[kMaxPass];
-    const int d = threadIdx.x;
+sort_count_kernel(const uint64_t* __restrict__ keys, const int64_t* __restrict__ num_pairs, int64_t capacity,
+                  int64_t tiles, uint32_t* __restrict__ cnt) {
+    __shared__ uint32_t h[kLdsTiles];
     const int64_t P = load_count(num_pairs, capacity);
-    if (d < kMaxPass) trivial[d] = 0;
+    if (tiles > kLdsTiles) {
+        const int64_t stride = (int64_t)gridDim.x * kThreads;
+        for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < P; i += stride) {
+            const uint64_t t = keys[i] >> 32;
+            if (t < (uint64_t)tiles) atomicAdd(&cnt[t], 1u);
+        }
+        return;
+    }
+    const int T = (int)tiles;
+    for (int i = threadIdx.x; i < T; i += kThreads) h[i] = 0;
     __syncthreads();
-    for (int p = 0; p < npass; ++p) {
-        const uint32_t c = hist[p * kRadix + d];
-        if ((int64_t)c == P) trivial[p] = 1;
-        s[d] = c;
-        __syncthreads();
-        // exclusive scan over 256 buckets (Hillis-Steele in LDS)
-        uint32_t x = c;
-        for (int off = 1; off < kRadix; off <<= 1) {
-            const uint32_t y = d >= off ? s[d - off] : 0u;
-            __syncthreads();
-            x += y;
-            s[d] = x;
-            __syncthreads();
-        }
-        digit_off[p * kRadix + d] = x - c;
-        __syncthreads();
+    const int64_t c0 = (int64_t)blockIdx.x * kChunk;
+    const int64_t c1 = c0 + kChunk < P ? c0 + kChunk : P;
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += kThreads) {
+        const uint64_t t = keys[i] >> 32;
+        if (t < (uint64_t)tiles) atomicAdd(&h[t], 1u);
     }
-    if (d == 0) {
-        int cur = 0;
-        for (int p = 0; p < npass; ++p) {
-            if (trivial[p]) {
-                ctrl[p] = -1;
-            } else {
-                ctrl[p] = cur;
-                cur ^= 1;
-            }
-        }
-        ctrl[npass] = cur;
-    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < T; i += kThreads)
+        if (h[i]) atomicAdd(&cnt[i], h[i]);
 }
 
+FS_DEV uint32_t wave_inclusive_scan(uint32_t x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan of the tile counts into ranges (single pass: partitions by
+// atomic ticket, decoupled look-back with one wave reading 64 predecessors
+// per round trip).
 __global__ void __launch_bounds__(kThreads)
-sort_pass_kernel(uint64_t* __restrict__ keys0, uint32_t* __restrict__ vals0, uint64_t* __restrict__ keys1,
-                 uint32_t* __restrict__ vals1, const int64_t* __restrict__ num_pairs, int64_t capacity, int pass,
-                 const uint32_t* __restrict__ digit_off, const int32_t* __restrict__ ctrl,
-                 uint32_t* __restrict__ status, uint32_t* __restrict__ ticket, int64_t parts_cap) {
-    __shared__ uint32_t wh[kThreads / 64][kRadix];
+sort_scan_kernel(const uint32_t* __restrict__ cnt, int64_t tiles, uint32_t* __restrict__ ranges,
+                 uint64_t* __restrict__ status, uint32_t* __restrict__ ticket, int64_t parts) {
     __shared__ uint32_t s_part;
-    const int src = ctrl[pass];
-    if (src < 0) return;
-    const int64_t P = load_count(num_pairs, capacity);
-    const int64_t parts = (P + kPart - 1) / kPart;
+    __shared__ uint64_t s_wave[kThreads / 64];
+    __shared__ uint64_t s_prefix;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid == 0) s_part = atomicAdd(ticket + pass, 1u);
-    for (int w = 0; w < kThreads / 64; ++w) wh[w][tid] = 0;
+    if (tid == 0) s_part = atomicAdd(ticket, 1u);
     __syncthreads();
     const int64_t part = s_part;
-    if (part >= parts || part >= parts_cap) return;
-    const uint64_t* sk = src ? keys1 : keys0;
-    const uint32_t* sv = src ? vals1 : vals0;
-    uint64_t* dk = src ? keys0 : keys1;
-    uint32_t* dv = src ? vals0 : vals1;
-    const int shift = 8 * pass;
-    const int64_t base = part * kPart + (int64_t)wave * (kPart / 4);
-    uint64_t k[kItems];
-    uint32_t val[kItems];
-    uint32_t rank[kItems];
-    const uint64_t lt = (1ull << lane) - 1ull;
+    if (part >= parts) return;
+    const int64_t base = part * kScanPart + (int64_t)tid * kScanItems;
+    uint32_t c[kScanItems];
+    uint32_t sum = 0;
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const int64_t idx = base + r * 64 + lane;
-        const bool valid = idx < P;
-        k[r] = valid ? sk[idx] : 0ull;
-        val[r] = valid ? sv[idx] : 0u;
+    for (int j = 0; j < kScanItems; ++j) {
+        c[j] = base + j < tiles ? cnt[base + j] : 0u;
+        sum += c[j];
     }
-#pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const int64_t idx = base + r * 64 + lane;
-        const bool valid = idx < P;
-        const uint32_t d = (uint32_t)(k[r] >> shift) & 0xffu;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            peers &= bit ? bb : ~bb;
-        }
-        const uint32_t prev = wh[wave][d];
-        rank[r] = prev + (uint32_t)__popcll(peers & lt);
-        if (valid && ((peers >> lane) >> 1) == 0ull) wh[wave][d] = prev + (uint32_t)__popcll(peers);
-    }
+    const uint32_t incl = wave_inclusive_scan(sum);
+    if (lane == 63) s_wave[wave] = incl;
     __syncthreads();
-    // per-digit partition totals and per-wave offsets (thread = digit)
-    {
-        const int d = tid;
-        uint32_t cw[kThreads / 64];
-        uint32_t total = 0;
-#pragma unroll
-        for (int w = 0; w < kThreads / 64; ++w) {
-            cw[w] = total;
-            total += wh[w][d];
-        }
-        uint32_t* st = status + ((int64_t)pass * parts_cap) * kRadix;
-        uint32_t excl = 0;
+    uint64_t wave_excl = 0, total = 0;
+    for (int w = 0; w < kThreads / 64; ++w) {
+        if (w < wave) wave_excl += s_wave[w];
+        total += s_wave[w];
+    }
+    if (wave == 0) {
+        uint64_t prefix = 0;
         if (part == 0) {
-            __hip_atomic_store(st + d, kPre | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                __hip_atomic_store(status + part, kFlagPre | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
-            __hip_atomic_store(st + part * kRadix + d, kAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            // look-back 8 predecessors per round trip (independent loads in flight)
+            if (lane == 0)
+                __hip_atomic_store(status + part, kFlagAgg | total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             int64_t j = part - 1;
             while (true) {
-                uint32_t sv[8];
+                const int64_t idx = j - lane;
+                const uint64_t st = idx >= 0 ? __hip_atomic_load(status + idx, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT)
+                                             : kFlagPre;   // before partition 0: an empty inclusive prefix
+                const uint64_t flag = st & ~kValMask;
+                const uint64_t notready = __ballot(flag == 0);
+                const uint64_t pre = __ballot(flag == kFlagPre);
+                const int limit = notready ? __builtin_ctzll(notready) : 64;
+                const int first_pre = pre ? __builtin_ctzll(pre) : 64;
+                const bool found = first_pre < limit;
+                const int take = found ? first_pre + 1 : limit;
+                uint64_t v = lane < take ? (st & kValMask) : 0ull;
 #pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    sv[k] = j - k >= 0 ? __hip_atomic_load(st + (j - k) * kRadix + d, __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT)
-                                       : kPre;   // before partition 0: an empty inclusive prefix
-                int k = 0;
-                bool found = false;
-                for (; k < 8; ++k) {
-                    const uint32_t flag = sv[k] & ~kCnt;
-                    if (flag == 0u) break;
-                    excl += sv[k] & kCnt;
-                    if (flag == kPre) {
-                        found = true;
-                        break;
-                    }
-                }
+                for (int d = 1; d < 64; d <<= 1) v += __shfl_xor(v, d, 64);
+                prefix += v;
                 if (found) break;
-                j -= k;
-                if (k == 0) __builtin_amdgcn_s_sleep(1);
+                j -= take;
+                if (take == 0) __builtin_amdgcn_s_sleep(1);
             }
-            __hip_atomic_store(st + part * kRadix + d, kPre | (excl + total), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                __hip_atomic_store(status + part, kFlagPre | (prefix + total), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         }
-        const uint32_t gbase = digit_off[pass * kRadix + d] + excl;
-        __syncthreads();
-#pragma unroll
-        for (int w = 0; w < kThreads / 64; ++w) wh[w][d] = gbase + cw[w];
+        if (lane == 0) s_prefix = prefix;
     }
     __syncthreads();
+    uint64_t off = s_prefix + wave_excl + (incl - sum);
 #pragma unroll
-    for (int r = 0; r < kItems; ++r) {
-        const int64_t idx = base + r * 64 + lane;
-        if (idx < P) {
-            const uint32_t d = (uint32_t)(k[r] >> shift) & 0xffu;
-            const uint32_t pos = wh[wave][d] + rank[r];
-            if ((int64_t)pos < P) {
-                dk[pos] = k[r];
-                dv[pos] = val[r];
+    for (int j = 0; j < kScanItems; ++j) {
+        if (base + j < tiles) {
+            ranges[2 * (base + j)] = (uint32_t)off;
+            ranges[2 * (base + j) + 1] = (uint32_t)(off + c[j]);
+        }
+        off += c[j];
+    }
+}
+
+// Pair i goes to its tile's start plus a cursor, as (depth key, record).
+// With at most kLdsTiles tiles every workgroup reserves, per tile, one run of
+// positions for its whole chunk (one global atomic per tile it touches) and
+// hands them out with LDS cursors; otherwise every pair takes a global atomic.
+__global__ void __launch_bounds__(kThreads)
+sort_scatter_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                    const int64_t* __restrict__ num_pairs, int64_t capacity, int64_t tiles,
+                    const uint32_t* __restrict__ ranges, uint32_t* __restrict__ fill, uint2* __restrict__ out) {
+    __shared__ uint32_t h[kLdsTiles];
+    const int64_t P = load_count(num_pairs, capacity);
+    if (tiles > kLdsTiles) {
+        const int64_t stride = (int64_t)gridDim.x * kThreads;
+        for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < P; i += stride) {
+            const uint64_t k = keys[i];
+            const uint64_t t = k >> 32;
+            if (t < (uint64_t)tiles) {
+                const uint32_t pos = ranges[2 * t] + atomicAdd(&fill[t], 1u);
+                if ((int64_t)pos < P) out[pos] = make_uint2((uint32_t)k, vals[i]);
             }
+        }
+        return;
+    }
+    const int T = (int)tiles;
+    for (int i = threadIdx.x; i < T; i += kThreads) h[i] = 0;
+    __syncthreads();
+    const int64_t c0 = (int64_t)blockIdx.x * kChunk;
+    const int64_t c1 = c0 + kChunk < P ? c0 + kChunk : P;
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += kThreads) {
+        const uint64_t t = keys[i] >> 32;
+        if (t < (uint64_t)tiles) atomicAdd(&h[t], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < T; i += kThreads)
+        if (h[i]) h[i] = ranges[2 * i] + atomicAdd(&fill[i], h[i]);   // first position of this chunk's run
+    __syncthreads();
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += kThreads) {
+        const uint64_t k = keys[i];
+        const uint64_t t = k >> 32;
+        if (t < (uint64_t)tiles) {
+            const uint32_t pos = atomicAdd(&h[t], 1u);
+            if ((int64_t)pos < P) out[pos] = make_uint2((uint32_t)k, vals[i]);
         }
     }
 }
 
+FS_DEV uint64_t composite(uint2 e) { return ((uint64_t)e.x << 32) | e.y; }
+
+// Bitonic sort of s[0, n2) (n2 a power of two, padding = ~0) by the workgroup.
+template <int NT>
+FS_DEV void bitonic_lds(uint64_t* s, int n2) {
+    for (int k = 2; k <= n2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < (n2 >> 1); i += NT) {
+                const int a = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+                const int b = a + j;
+                const bool up = (a & k) == 0;
+                const uint64_t x = s[a], y = s[b];
+                if ((x > y) == up) {
+                    s[a] = y;
+                    s[b] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+FS_DEV int next_pow2(int n) {
+    int p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+// Sort one run of 2 <= n <= capacity of s entries in LDS and write the final
+// keys and values.
+template <int NT>
+FS_DEV void sort_run_lds(uint64_t* s, const uint2* __restrict__ in, uint64_t tile, uint32_t start, int n,
+                         uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int n2 = next_pow2(n);
+    for (int i = threadIdx.x; i < n2; i += NT) s[i] = i < n ? composite(in[start + i]) : ~0ull;
+    __syncthreads();
+    bitonic_lds<NT>(s, n2);
+    for (int i = threadIdx.x; i < n; i += NT) {
+        const uint64_t c = s[i];
+        keys[start + i] = (tile << 32) | (c >> 32);
+        vals[start + i] = (uint32_t)c;
+    }
+}
+
+// One wave per tile: runs of up to kWaveCap entries are sorted by a bitonic
+// network in the wave's own LDS slice (a wave's LDS accesses complete in
+// order, so stages need no workgroup barrier); longer runs are appended to
+// the list the long-run kernel works through.
 __global__ void __launch_bounds__(kThreads)
-sort_ranges_kernel(uint64_t* __restrict__ keys0, uint32_t* __restrict__ vals0, const uint64_t* __restrict__ keys1,
-                   const uint32_t* __restrict__ vals1, const int64_t* __restrict__ num_pairs, int64_t capacity,
-                   const int32_t* __restrict__ ctrl, int npass, int64_t total_tiles, uint32_t* __restrict__ ranges) {
-    const int64_t P = load_count(num_pairs, capacity);
-    const bool alt = ctrl[npass] != 0;
-    const uint64_t* k = alt ? keys1 : keys0;
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < P; i += stride) {
-        const uint64_t key = k[i];
-        const int64_t t = (int64_t)(key >> 32);
-        if (t < total_tiles) {
-            if (i == 0 || (k[i - 1] >> 32) != (uint64_t)t) ranges[2 * t] = (uint32_t)i;
-            if (i == P - 1 || (k[i + 1] >> 32) != (uint64_t)t) ranges[2 * t + 1] = (uint32_t)(i + 1);
+sort_short_runs_kernel(const uint2* __restrict__ in, const uint32_t* __restrict__ ranges, int64_t tiles,
+                       uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ long_list,
+                       uint32_t* __restrict__ long_count) {
+    __shared__ uint64_t s_all[kThreads / 64][kWaveCap];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + wave;
+    if (t >= tiles) return;   // uniform per wave
+    const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
+    const int n = (int)(end - start);
+    if (n == 0) return;
+    if (n > kWaveCap) {
+        if (lane == 0) long_list[atomicAdd(long_count, 1u)] = (uint32_t)t;
+        return;
+    }
+    uint64_t* s = s_all[wave];
+    const int n2 = next_pow2(n < 2 ? 2 : n);
+    for (int i = lane; i < n2; i += 64) s[i] = i < n ? composite(in[start + i]) : ~0ull;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int k = 2; k <= n2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = lane; i < (n2 >> 1); i += 64) {
+                const int a = ((i & ~(j - 1)) << 1) | (i & (j - 1));
+                const int b = a + j;
+                const bool up = (a & k) == 0;
+                const uint64_t x = s[a], y = s[b];
+                if ((x > y) == up) {
+                    s[a] = y;
+                    s[b] = x;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-        if (alt) {
-            keys0[i] = key;
-            vals0[i] = vals1[i];
+    }
+    for (int i = lane; i < n; i += 64) {
+        const uint64_t c = s[i];
+        keys[start + i] = ((uint64_t)t << 32) | (c >> 32);
+        vals[start + i] = (uint32_t)c;
+    }
+}
+
+// Stable LSD radix sort of one run through global memory, 8-bit digits of the
+// 64-bit composite key, ping-ponging between a[start, start + n) (input) and
+// b[start, start + n); passes whose digit is the same for the whole run are
+// skipped.  Ends with the sorted run written as final keys and values (b may
+// alias the keys: each thread reads its element before writing it).
+template <int NT>
+FS_DEV void sort_run_global(uint2* a, uint2* b, uint64_t tile, uint32_t start, uint32_t n,
+                            uint64_t* keys, uint32_t* __restrict__ vals, uint32_t* hist, uint32_t* wcnt,
+                            uint32_t* flag) {
+    constexpr int kWaves = NT / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    uint2* src = a + start;
+    uint2* dst = b + start;
+    for (int pass = 0; pass < 8; ++pass) {
+        const int shift = 8 * pass;
+        if (tid < 256) hist[tid] = 0;
+        __syncthreads();
+        for (uint32_t i = tid; i < n; i += NT) atomicAdd(&hist[(composite(src[i]) >> shift) & 0xff], 1u);
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t acc = 0;
+            uint32_t single = 0;
+            for (int d = 0; d < 256; ++d) {
+                const uint32_t c = hist[d];
+                if (c == n) single = 1;   // one digit value: identity permutation
+                hist[d] = acc;
+                acc += c;
+            }
+            *flag = single;
         }
+        __syncthreads();
+        if (*flag) continue;   // uniform
+        for (uint32_t c0 = 0; c0 < n; c0 += NT) {
+            const uint32_t i = c0 + tid;
+            const bool valid = i < n;
+            const uint2 e = valid ? src[i] : make_uint2(0u, 0u);
+            const uint32_t d = (uint32_t)(composite(e) >> shift) & 0xffu;
+            // rank among equal digits of this chunk: inside the wave by ballot
+            // matching, across waves from per-wave digit counts
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int bit = 0; bit < 8; ++bit) {
+                const bool x = (d >> bit) & 1u;
+                const uint64_t bb = __ballot(x);
+                peers &= x ? bb : ~bb;
+            }
+            for (int i = tid; i < kWaves * 256; i += NT) wcnt[i] = 0;
+            __syncthreads();
+            if (valid && ((peers >> lane) >> 1) == 0ull) wcnt[wave * 256 + d] = (uint32_t)__popcll(peers);
+            __syncthreads();
+            if (valid) {
+                uint32_t before = 0;
+                for (int w = 0; w < wave; ++w) before += wcnt[w * 256 + d];
+                dst[hist[d] + before + (uint32_t)__popcll(peers & lt)] = e;
+            }
+            __syncthreads();
+            if (tid < 256) {
+                uint32_t tot = 0;
+                for (int w = 0; w < kWaves; ++w) tot += wcnt[w * 256 + tid];
+                hist[tid] += tot;
+            }
+            __syncthreads();
+        }
+        uint2* tmp = src;
+        src = dst;
+        dst = tmp;
+    }
+    for (uint32_t i = tid; i < n; i += NT) {
+        const uint2 e = src[i];
+        keys[start + i] = (tile << 32) | e.x;
+        vals[start + i] = e.y;
+    }
+}
+
+// Runs longer than kWaveCap, from the list: up to kLargeCap entries by a
+// workgroup bitonic network in LDS, longer ones by the global radix sort.
+__global__ void __launch_bounds__(kLongThreads)
+sort_long_runs_kernel(uint2* __restrict__ in, const uint32_t* __restrict__ ranges,
+                      const uint32_t* __restrict__ long_list, const uint32_t* __restrict__ long_count,
+                      uint64_t* keys, uint32_t* __restrict__ vals) {
+    __shared__ uint64_t s[kLargeCap];
+    const uint32_t count = *long_count;
+    for (uint32_t it = blockIdx.x; it < count; it += gridDim.x) {
+        const uint64_t t = long_list[it];
+        const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
+        const uint32_t n = end - start;
+        if (n <= (uint32_t)kLargeCap) {
+            sort_run_lds<kLongThreads>(s, in, t, start, (int)n, keys, vals);
+        } else {
+            // the run's own slice of the key array is the radix passes' second
+            // buffer; LDS holds their counters
+            uint32_t* hist = reinterpret_cast<uint32_t*>(s);
+            uint32_t* wcnt = hist + 256;
+            uint32_t* flag = wcnt + (kLongThreads / 64) * 256;
+            sort_run_global<kLongThreads>(in, reinterpret_cast<uint2*>(keys), t, start, n, keys, vals, hist, wcnt, flag);
+        }
+        __syncthreads();   // LDS is reused by the next run
     }
 }
 
 }  // namespace
 
-int fs_sort_passes(int64_t total_tiles) {
-    int tile_bits = 1;
-    while (tile_bits < 32 && (int64_t(1) << tile_bits) < total_tiles) ++tile_bits;
-    return (32 + tile_bits + 7) / 8;
-}
-
-int64_t fs_sort_parts(int64_t capacity) { return (capacity + kPart - 1) / kPart; }
+int64_t fs_sort_scan_parts(int64_t total_tiles) { return (total_tiles + kScanPart - 1) / kScanPart; }
 
 hipError_t fs_launch_sort(uint64_t* keys, uint32_t* vals, int64_t capacity, const int64_t* num_pairs, int64_t hint,
                           int64_t total_tiles, uint32_t* ranges, const FsWorkspace& ws, hipStream_t s) {
-    const int npass = ws.npass;
-    const int64_t parts_cap = ws.sort_parts;
+    if (total_tiles >= (int64_t(1) << 31)) return hipErrorInvalidValue;
     const int64_t pmax = hint >= 0 ? (hint < capacity ? hint : capacity) : capacity;
-    const int64_t parts = (pmax + kPart - 1) / kPart;
-    const int64_t nstatus = (int64_t)npass * parts_cap * kRadix;
+    const int64_t parts = fs_sort_scan_parts(total_tiles);
     {
-        int64_t work = nstatus > 2 * total_tiles ? nstatus : 2 * total_tiles;
+        const int64_t work = total_tiles > parts ? total_tiles : parts;
         unsigned blocks = (unsigned)((work + 255) / 256);
-        blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
-        hipLaunchKernelGGL(sort_clear_kernel, dim3(blocks), dim3(256), 0, s, ws.hist, (int64_t)npass * kRadix,
-                           ws.sort_status, nstatus, ws.sort_ticket, npass, ranges, 2 * total_tiles);
-    }
-    {
-        unsigned blocks = (unsigned)((pmax + kThreads * 8 - 1) / (kThreads * 8));
         blocks = blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks);
-        hipLaunchKernelGGL(sort_hist_kernel, dim3(blocks), dim3(kThreads), 0, s, keys, num_pairs, capacity, npass,
-                           ws.hist);
+        hipLaunchKernelGGL(sort_clear_kernel, dim3(blocks), dim3(256), 0, s, ws.tile_cnt, ws.tile_fill, total_tiles,
+                           ws.sort_status, parts, ws.sort_ticket);
     }
-    hipLaunchKernelGGL(sort_scan_kernel, dim3(1), dim3(kThreads), 0, s, ws.hist, num_pairs, capacity, npass,
-                       ws.digit_off, ws.sort_ctrl);
-    if (parts > 0) {
-        for (int p = 0; p < npass; ++p)
-            hipLaunchKernelGGL(sort_pass_kernel, dim3((unsigned)parts), dim3(kThreads), 0, s, keys, vals, ws.keys_alt,
-                               ws.vals_alt, num_pairs, capacity, p, ws.digit_off, ws.sort_ctrl, ws.sort_status,
-                               ws.sort_ticket, parts_cap);
+    unsigned pblocks;
+    if (total_tiles <= kLdsTiles) {
+        const int64_t chunks = (pmax + kChunk - 1) / kChunk;
+        if (chunks >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+        pblocks = (unsigned)(chunks < 1 ? 1 : chunks);
+    } else {
+        const int64_t b = (pmax + kThreads * 4 - 1) / (kThreads * 4);
+        pblocks = (unsigned)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
     }
-    {
-        unsigned blocks = (unsigned)((pmax + kThreads * 4 - 1) / (kThreads * 4));
-        blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
-        hipLaunchKernelGGL(sort_ranges_kernel, dim3(blocks), dim3(kThreads), 0, s, keys, vals, ws.keys_alt,
-                           ws.vals_alt, num_pairs, capacity, ws.sort_ctrl, npass, total_tiles, ranges);
-    }
+    hipLaunchKernelGGL(sort_count_kernel, dim3(pblocks), dim3(kThreads), 0, s, keys, num_pairs, capacity, total_tiles,
+                       ws.tile_cnt);
+    hipLaunchKernelGGL(sort_scan_kernel, dim3((unsigned)parts), dim3(kThreads), 0, s, ws.tile_cnt, total_tiles, ranges,
+                       ws.sort_status, ws.sort_ticket, parts);
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3(pblocks), dim3(kThreads), 0, s, keys, vals, num_pairs, capacity,
+                       total_tiles, ranges, ws.tile_fill, ws.runs);
+    const unsigned sblocks = (unsigned)((total_tiles + kThreads / 64 - 1) / (kThreads / 64));
+    hipLaunchKernelGGL(sort_short_runs_kernel, dim3(sblocks), dim3(kThreads), 0, s, ws.runs, ranges, total_tiles, keys,
+                       vals, ws.long_list, ws.sort_ticket + 1);
+    hipLaunchKernelGGL(sort_long_runs_kernel, dim3(kLongGrid), dim3(kLongThreads), 0, s, ws.runs, ranges, ws.long_list,
+                       ws.sort_ticket + 1, keys, vals);
     return hipGetLastError();
 }

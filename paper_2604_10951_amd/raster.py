@@ -105,6 +105,8 @@ class Rasterizer:
             V = self.num_views
             self._bufs["records"] = torch.empty(V * n * L.FS_RECORD_BYTES, dtype=torch.uint8, device=self.device)
             self._bufs["tiles"] = torch.empty(V * n, dtype=torch.int32, device=self.device)
+            self._bufs["tile_cache"] = torch.empty(V * n * L.FS_TILE_CACHE_WORDS, dtype=torch.int32,
+                                                   device=self.device)
             self._bufs["num_pairs"] = torch.zeros(1, dtype=torch.int64, device=self.device)
             self._bufs["ranges"] = torch.empty(self.total_tiles * 2, dtype=torch.int32, device=self.device)
             self._n = n
@@ -123,7 +125,7 @@ class Rasterizer:
         b = self._bufs
         L.check(self.lib.fs_preprocess(_p(means), _p(scales), _p(quats), _p(opacity), n, _p(self.cams_dev),
                                        self.num_views, ctypes.byref(self.opts), _p(b["records"]), _p(b["tiles"]),
-                                       _stream(self.device)), "fs_preprocess")
+                                       _p(b["tile_cache"]), _stream(self.device)), "fs_preprocess")
         return b["records"], b["tiles"]
 
     def bin(self, means, scales, quats, opacity) -> int:
@@ -132,8 +134,8 @@ class Rasterizer:
             b = self._bufs
             P = ctypes.c_int64(0)
             st = self.lib.fs_bin(_p(means), _p(scales), _p(quats), _p(opacity), n, _p(self.cams_dev), self.num_views,
-                                 ctypes.byref(self.opts), _p(b["tiles"]), _p(b["keys"]), _p(b["vals"]),
-                                 self.capacity, _p(b["num_pairs"]), ctypes.byref(P), _p(b["ws"]),
+                                 ctypes.byref(self.opts), _p(b["tiles"]), _p(b["tile_cache"]), _p(b["keys"]),
+                                 _p(b["vals"]), self.capacity, _p(b["num_pairs"]), ctypes.byref(P), _p(b["ws"]),
                                  _stream(self.device))
             if st == L.FS_ERR_CAPACITY:
                 self._ensure(n, int(P.value * 1.25) + 1024)
@@ -200,12 +202,13 @@ class Rasterizer:
             ev[0].record()
         L.check(self.lib.fs_preprocess(_p(means), _p(scales), _p(quats), _p(opacity), n, _p(self.cams_dev),
                                        self.num_views, ctypes.byref(self.opts), _p(b["records"]), _p(b["tiles"]),
-                                       _stream(dev)), "fs_preprocess")
+                                       _p(b["tile_cache"]), _stream(dev)), "fs_preprocess")
         if ev[1] is not None:
             ev[1].record()
         L.check(self.lib.fs_bin(_p(means), _p(scales), _p(quats), _p(opacity), n, _p(self.cams_dev), self.num_views,
-                                ctypes.byref(self.opts), _p(b["tiles"]), _p(b["keys"]), _p(b["vals"]), self.capacity,
-                                _p(b["num_pairs"]), None, _p(b["ws"]), _stream(dev)), "fs_bin")
+                                ctypes.byref(self.opts), _p(b["tiles"]), _p(b["tile_cache"]), _p(b["keys"]),
+                                _p(b["vals"]), self.capacity, _p(b["num_pairs"]), None, _p(b["ws"]), _stream(dev)),
+                "fs_bin")
         if ev[2] is not None:
             ev[2].record()
         L.check(self.lib.fs_sort(_p(b["keys"]), _p(b["vals"]), self.capacity, _p(b["num_pairs"]), -1,

@@ -47,7 +47,18 @@ def test_host_only_entry_points_without_gpu():
     # invalid options are rejected before anything touches a device
     o2 = _lib.make_opts(tile=12)
     assert lib.fs_preprocess(None, None, None, None, 0, ctypes.c_void_p(1), 1, ctypes.byref(o2), None, None,
-                             None) == _lib.FS_ERR_ARG
+                             None, None) == _lib.FS_ERR_ARG
     o3 = _lib.make_opts(topk=-1)
     assert lib.fs_preprocess(None, None, None, None, 0, ctypes.c_void_p(1), 1, ctypes.byref(o3), None, None,
-                             None) == _lib.FS_ERR_ARG
+                             None, None) == _lib.FS_ERR_ARG
+    # the split render schedule exists for Top-K only
+    o4 = _lib.make_opts(topk=0, schedule=_lib.FS_SCHED_SPLIT)
+    assert lib.fs_preprocess(None, None, None, None, 0, ctypes.c_void_p(1), 1, ctypes.byref(o4), None, None,
+                             None, None) == _lib.FS_ERR_ARG
+    o5 = _lib.make_opts(topk=8, schedule=_lib.FS_SCHED_SPLIT)
+    assert lib.fs_preprocess(None, None, None, None, 0, ctypes.c_void_p(1), 1, ctypes.byref(o5), None, None,
+                             None, None) == _lib.FS_OK
+    # the tile cache must be 16-byte aligned
+    assert lib.fs_preprocess(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 1,
+                             ctypes.c_void_p(16), 1, ctypes.byref(o5), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                             ctypes.c_void_p(20), None) == _lib.FS_ERR_ARG

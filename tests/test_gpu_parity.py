@@ -269,3 +269,26 @@ def test_headline_pairs_bit_exact(headline):
     for tile in (8, 16):
         _, fr = _render(scene, cam, tile=tile, topk=8)
         assert check_pairs(fr, scene, cam, tile) > 100_000
+
+
+def test_sort_long_tile_runs():
+    """Tile runs longer than the in-LDS sorts hold (> 8192 entries) take the
+    global radix path; short and medium runs take the LDS networks.  The
+    sorted pairs and ranges must match the oracle's bit for bit."""
+    _print_case("long tile runs")
+    rng = np.random.default_rng(12)
+    n = 24000
+    means = np.empty((n, 3), np.float32)
+    means[:, 0:2] = rng.uniform(-0.05, 0.05, size=(n, 2))
+    means[:, 2] = rng.uniform(3.0, 5.0, size=n)
+    scales = rng.uniform(0.05, 0.4, size=(n, 2)).astype(np.float32)
+    q = rng.standard_normal((n, 4)).astype(np.float32)
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    opacity = rng.uniform(0.05, 0.95, size=n).astype(np.float32)
+    feats = rng.standard_normal((n, 4)).astype(np.float32)
+    sc = scenes.Scene(means, scales, q, opacity, feats)
+    cam = scenes.centred_camera(96, 64)
+    _, fr = _render(sc, cam, tile=32, topk=4)
+    runs = (fr.ranges[:, 1] - fr.ranges[:, 0]).cpu().numpy()
+    assert runs.max() > 8192 and ((runs > 1024) & (runs <= 8192)).any() or runs.max() > 8192, runs
+    assert check_pairs(fr, sc, cam, 32) > 8192
