@@ -223,7 +223,11 @@ fs_status fs_render_forward(const void* records, const uint32_t* vals, const uin
  * FS_GRAD_RECORD_FLOATS floats (zeroed by this call).  Gradients are summed
  * with float atomics, so their last bits depend on scheduling.  C <= 128
  * (FS_ERR_UNSUPPORTED above).  The forward outputs out_T / out_last must come
- * from fs_render_forward on the same records, vals and tile_ranges.
+ * from fs_render_forward on the same records, vals and tile_ranges.  With
+ * topk > 0 the selection is recomputed exactly as the forward made it (the
+ * transmittance chain in the forward's double-precision order), in
+ * `workspace` (fs_workspace_bytes with the same opts), and out_T / out_n /
+ * out_last are not read.
  */
 fs_status fs_render_backward(const float* means, const float* scales, const float* quats, const float* opacity,
                              const void* records, const uint32_t* vals, const uint32_t* tile_ranges,

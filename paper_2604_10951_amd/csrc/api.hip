@@ -76,12 +76,15 @@ bool fs_workspace_layout(void* base, int64_t n, int32_t num_views, int64_t total
     w.render_offs = static_cast<uint32_t*>(take(sizeof(uint32_t) * 64));
     w.render_max_blocks = (total_tiles > 0 ? total_tiles : 1) * 16;
     w.render_order = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)w.render_max_blocks));
-    if (opts && opts->schedule == FS_SCHED_SPLIT && opts->topk > 0) {
+    if (opts && opts->topk > 0) {
+        // Top-K lists: the split forward and the Top-K backward
         const int64_t sb = opts->tile / 8;
-        w.topk_pair_slots = (total_tiles > 0 ? total_tiles : 1) * sb * sb * 64 * (int64_t)opts->topk;
+        const int64_t nblocks = (total_tiles > 0 ? total_tiles : 1) * sb * sb;
+        w.topk_pair_slots = nblocks * 64 * (int64_t)opts->topk;
         w.topk_pairs = static_cast<uint2*>(take(sizeof(uint2) * (size_t)w.topk_pair_slots));
         w.topk_rows = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)w.topk_pair_slots));
-        w.topk_nrows = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)(w.topk_pair_slots / (64 * opts->topk))));
+        w.topk_nrows = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)nblocks));
+        w.topk_counts = static_cast<int32_t*>(take(sizeof(int32_t) * (size_t)(nblocks * 64)));
     }
     const size_t render_bytes = align_up(off, 256);
     size_t total = bin_bytes > sort_bytes ? bin_bytes : sort_bytes;
@@ -208,7 +211,10 @@ fs_status fs_render_backward(const float* means, const float* scales, const floa
     if (C > 128) return FS_ERR_UNSUPPORTED;   // one channel chunk per block in the backward
     FsWorkspace ws;
     memset(&ws, 0, sizeof(ws));
-    (void)workspace;
+    if (opts->topk > 0) {
+        if (!workspace) return FS_ERR_ARG;
+        if (!fs_workspace_layout(workspace, 0, 1, total_tiles, 0, opts, &ws, nullptr)) return FS_ERR_ARG;
+    }
     return hip_status(fs_launch_render_backward(means, scales, quats, opacity, static_cast<const FsRecord*>(records),
                                                 vals, tile_ranges, feats, C, n, cams_dev, num_views, total_tiles,
                                                 *opts, out_T, out_n, out_last, grad_feat, grad_records, grad_means,

@@ -443,6 +443,14 @@ FS_DEV FsResp fs_response(const FsRecord& r, double dx, double dy) {
     return o;
 }
 
+// A pixel is accepted only inside the record's pixel box (it holds every
+// pixel centre inside the exact footprint conic; outside it the d2 test can
+// only pass by rounding).  Every renderer applies the same test, so their
+// accept decisions agree wherever they evaluate a pixel.
+FS_DEV bool fs_in_box(const FsRecord& r, int px, int py) {
+    return (px >= r.x0) & (px <= r.x1) & (py >= r.y0) & (py <= r.y1);
+}
+
 // Record index -> surfel index for record r = v * n + i.
 FS_DEV int64_t fs_surfel_of(int64_t rec, int64_t n) { return rec % n; }
 
@@ -489,6 +497,15 @@ FS_DEV BlockPos locate_block(int64_t b, int S, int RB, const fs_camera* cams, in
     return bp;
 }
 
+// Workgroup -> work item: dispatch hands workgroup g to XCD g mod 8; remap so
+// that XCD x takes the contiguous run [x * per, (x + 1) * per).  The last
+// G mod 8 workgroups keep their own index.
+FS_DEV int64_t xcd_remap(int64_t g, int64_t G) {
+    const int64_t per = G / 8;
+    if (g >= per * 8) return g;
+    return (g % 8) * per + g / 8;
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launch helpers implemented in the .hip files.
 // ---------------------------------------------------------------------------
@@ -520,6 +537,7 @@ struct FsWorkspace {
     uint32_t* topk_rows;
     uint32_t* topk_nrows;
     int64_t topk_pair_slots;
+    int32_t* topk_counts;    // backward: blend counts per pixel (at least 64 per 8x8 block)
 };
 
 bool fs_workspace_layout(void* base, int64_t n, int32_t num_views, int64_t total_tiles, int64_t pair_capacity,
@@ -547,6 +565,14 @@ hipError_t fs_launch_render_forward(const FsRecord* records, const uint32_t* val
 // order) into ws.render_order; zeroes ws.render_ticket.
 hipError_t fs_launch_block_order(const uint32_t* ranges, int sb2, uint32_t nblocks, const FsWorkspace& ws,
                                  hipStream_t s);
+
+// Selection pass of the split Top-K renderer alone: per-pixel (slot, weight)
+// lists, block row lists and counts in the workspace; out_T, out_last,
+// out_idx and counters optional.
+hipError_t fs_launch_topk_select(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges, int64_t n,
+                                 const fs_camera* cams, int num_views, int64_t total_tiles, const fs_opts& o,
+                                 float* out_T, int32_t* out_n, int32_t* out_last, int32_t* out_idx,
+                                 uint64_t* counters, const FsWorkspace& ws, hipStream_t s);
 
 hipError_t fs_launch_render_topk_split(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges,
                                        const void* feats, int C, int64_t n, const fs_camera* cams, int num_views,

@@ -42,6 +42,30 @@ FS_DEV float wave_sum(float x) {
     return x;
 }
 
+// dL/dalpha of one (pixel, record) contribution -> dL/dL (9, rows of the
+// record's coefficient matrix times (1, dx, dy)) and dL/do, through alpha = o
+// exp(-d2 / 2) (no gradient when clamped at alpha_max), d2 = u^2 + v^2 and
+// (u, v) = (h0, h1) / h2.
+FS_DEV void blend_chain(const FsRecord& r, const FsResp& rs, double ddx, double ddy, float Gs, float dalpha,
+                        float* g) {
+    g[9] = Gs * dalpha;   // dL/do
+    const float dG = r.o * dalpha;
+    const float dd2 = -0.5f * Gs * dG;
+    const float u = (float)rs.u, vv = (float)rs.v, rh = (float)rs.rh;
+    const float du = 2.f * u * dd2, dv = 2.f * vv * dd2;
+    const float dh0 = du * rh, dh1 = dv * rh, dh2 = -(u * du + vv * dv) * rh;
+    const float fx = (float)ddx, fy = (float)ddy;
+    g[0] = dh0;
+    g[1] = dh0 * fx;
+    g[2] = dh0 * fy;
+    g[3] = dh1;
+    g[4] = dh1 * fx;
+    g[5] = dh1 * fy;
+    g[6] = dh2;
+    g[7] = dh2 * fx;
+    g[8] = dh2 * fy;
+}
+
 __global__ void zero_f32_kernel(float* p, int64_t count) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0.f;
@@ -135,7 +159,7 @@ render_bwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
             if (r.x1 < wx0 || r.x0 > wx0 + 7 || r.y1 < wy0 || r.y0 > wy0 + 7) continue;
             if ((int)(b0 + e) > last) continue;
             const FsResp rs = fs_response(r, (double)(px - r.ax), (double)(py - r.ay));
-            if (rs.d2 <= r.k2) {
+            if (rs.d2 <= r.k2 && fs_in_box(r, px, py)) {
                 const float Gs = __builtin_amdgcn_exp2f(-0.72134752044448170f * (float)rs.d2);
                 const float alpha = fminf(o.alpha_max, r.o * Gs);
                 T = T / (1.0 - (double)alpha);
@@ -197,18 +221,7 @@ render_bwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
                 const float D = s_D[e][lane];
                 const float dalpha = Tm * D - suffix / (1.f - alpha);
                 suffix = fmaf(w, D, suffix);
-                if (!clamped) {
-                    g[9] = Gs * dalpha;                        // dL/do
-                    const float dG = r.o * dalpha;
-                    const float dd2 = -0.5f * Gs * dG;
-                    const float u = (float)rs.u, vv = (float)rs.v, rh = (float)rs.rh;
-                    const float du = 2.f * u * dd2, dv = 2.f * vv * dd2;
-                    const float dh0 = du * rh, dh1 = dv * rh, dh2 = -(u * du + vv * dv) * rh;
-                    const float fx = (float)ddx, fy = (float)ddy;
-                    g[0] = dh0; g[1] = dh0 * fx; g[2] = dh0 * fy;
-                    g[3] = dh1; g[4] = dh1 * fx; g[5] = dh1 * fy;
-                    g[6] = dh2; g[7] = dh2 * fx; g[8] = dh2 * fy;
-                }
+                if (!clamped) blend_chain(r, rs, ddx, ddy, Gs, dalpha, g);
             }
 #pragma unroll
             for (int k = 0; k < 10; ++k) {
@@ -340,6 +353,276 @@ preprocess_bwd_kernel(const float* __restrict__ means, const float* __restrict__
     go[i] += (float)ao;
 }
 
+// ---------------------------------------------------------------------------
+// Top-K backward.  The selection pass of the split forward recomputes every
+// pixel's (row slot, weight) list and every block's row list; then one
+// workgroup per 8x8 block:
+//   1. D = g . c for every (pixel, contributor): feature rows are staged in
+//      LDS windows (direct global -> LDS loads), TPP threads per pixel each
+//      hold one 16-byte channel vector of g in registers and reduce their
+//      partial dot products with shuffles inside the pixel's group; the same
+//      pass adds w g to per-row LDS accumulators (float atomics), flushed once
+//      per (block, row) to dL/dc;
+//   2. per contribution, all pairs of the block in parallel: alpha from the
+//      record; per pixel (LDS only) the forward's transmittance chain (double
+//      precision, same order) and the suffix sums S = sum_{l > m} w_l D_l;
+//      then the chain to dL/dL and dL/do, summed per row slot in LDS and
+//      flushed once per (block, slot).
+// ---------------------------------------------------------------------------
+constexpr int kGradThreads = 256;
+constexpr int kGradMaxK = 16;
+constexpr int kGradSlots = 256;   // row slots whose geometry gradients are summed in LDS
+
+template <typename FT>
+struct RowV;
+template <>
+struct RowV<float> {
+    static constexpr int VE = 4;
+    FS_DEV static void get(const uint4& r, float* f) {
+        f[0] = __uint_as_float(r.x);
+        f[1] = __uint_as_float(r.y);
+        f[2] = __uint_as_float(r.z);
+        f[3] = __uint_as_float(r.w);
+    }
+};
+template <>
+struct RowV<uint16_t> {
+    static constexpr int VE = 8;
+    FS_DEV static void get(const uint4& r, float* f) {
+        const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            f[2 * i] = __uint_as_float(w[i] << 16);
+            f[2 * i + 1] = __uint_as_float(w[i] & 0xffff0000u);
+        }
+    }
+};
+
+template <typename FT, int TPP>
+__global__ void __launch_bounds__(kGradThreads)
+topk_grad_kernel(const FsRecord* __restrict__ records, const uint2* __restrict__ pairs,
+                 const int32_t* __restrict__ counts, const uint32_t* __restrict__ rows,
+                 const uint32_t* __restrict__ nrows, const FT* __restrict__ feats, int C, int K, int64_t n,
+                 const fs_camera* __restrict__ cams, int num_views, int S, int64_t nblocks, fs_opts o,
+                 const float* __restrict__ grad_feat, float* __restrict__ grad_records,
+                 float* __restrict__ grad_feats) {
+    constexpr int VE = RowV<FT>::VE;
+    constexpr int kGroups = kGradThreads / TPP;   // row slots handled at once
+    constexpr int kPairs = 64 * kGradMaxK;
+    __shared__ uint2 s_pairs[kPairs];
+    __shared__ float s_D[kPairs];
+    __shared__ float s_S[kPairs];    // alpha, then the transmittance before the contribution
+    __shared__ float s_T2[kPairs];   // alpha
+    __shared__ float s_U[kPairs];    // suffix sums S = sum_{l > m} w_l D_l
+    __shared__ int s_soff[kPairs + 1];       // per row slot: first entry of its pair list
+    __shared__ int s_sfill[kPairs];          // per row slot: pairs, then the fill cursor
+    __shared__ uint16_t s_list[kPairs];      // pair indices p * K + j grouped by row slot
+    __shared__ int s_cnt[64];
+    __shared__ int s_wave[kGradThreads / 64];
+    __shared__ float s_grec[kGradSlots][10];   // dL/dL and dL/do of the first kGradSlots row slots
+    const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t block = xcd_remap(blockIdx.x, nblocks);
+    const BlockPos bp = locate_block(block, S, 8, cams, num_views);
+    if (!bp.valid) return;           // uniform
+    const uint32_t R = nrows[block];
+    if (R == 0) return;              // no pixel of the block blended anything
+    const fs_camera& cam = cams[bp.view];
+    const int nv = C / VE;           // channel vectors per row (C % VE == 0)
+    const int q = tid % TPP, grp = tid / TPP;
+    const bool has_vec = q < nv;
+    const uint32_t* __restrict__ rowlist = rows + block * 64 * (int64_t)K;
+    const int npairs = 64 * K;
+    for (int t = tid; t < npairs; t += kGradThreads) {
+        s_pairs[t] = pairs[block * 64 * (int64_t)K + t];
+        s_sfill[t] = 0;
+    }
+    if (tid < 64) {
+        const int px = bp.x0 + (tid & 7), py = bp.y0 + (tid >> 3);
+        s_cnt[tid] = (px < cam.width && py < cam.height) ? counts[cam.pixel_offset + (int64_t)py * cam.width + px] : 0;
+    }
+    __syncthreads();
+    // 1a. pairs grouped by row slot (counting sort in LDS)
+    for (int t = tid; t < npairs; t += kGradThreads)
+        if (t % K < s_cnt[t / K]) atomicAdd(&s_sfill[s_pairs[t].x], 1);
+    __syncthreads();
+    {
+        constexpr int kPer = (kPairs + kGradThreads - 1) / kGradThreads;
+        const int b0 = tid * kPer;
+        int c[kPer];
+        int sum = 0;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            c[i] = b0 + i < (int)R ? s_sfill[b0 + i] : 0;
+            sum += c[i];
+        }
+        int incl = sum;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += y;
+        }
+        if (lane == 63) s_wave[wave] = incl;
+        __syncthreads();
+        int off = incl - sum;
+        for (int w = 0; w < wave; ++w) off += s_wave[w];
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            if (b0 + i < (int)R) {
+                s_soff[b0 + i] = off;
+                s_sfill[b0 + i] = 0;
+            }
+            off += c[i];
+        }
+        if (tid == kGradThreads - 1) s_soff[R] = off;
+    }
+    __syncthreads();
+    for (int t = tid; t < npairs; t += kGradThreads)
+        if (t % K < s_cnt[t / K]) {
+            const uint32_t slot = s_pairs[t].x;
+            s_list[s_soff[slot] + atomicAdd(&s_sfill[slot], 1)] = (uint16_t)t;
+        }
+    __syncthreads();
+    // 1b. slot-major: a group of TPP threads owns a row slot and one channel
+    //     vector per thread; it reads the feature row once and, over the
+    //     slot's pixels, forms D = g . c (shuffle reduction inside the group)
+    //     and dL/dc = sum w g in registers, flushed once per (block, slot)
+    for (uint32_t s0 = 0; s0 < R; s0 += kGroups) {
+        const uint32_t slot = s0 + (uint32_t)grp;
+        const bool live = slot < R;   // uniform inside the group
+        float f[VE], acc[VE];
+#pragma unroll
+        for (int i = 0; i < VE; ++i) acc[i] = f[i] = 0.f;
+        uint32_t sidx = 0;
+        if (live) {
+            sidx = rowlist[slot];
+            if (has_vec) RowV<FT>::get(*reinterpret_cast<const uint4*>(feats + (int64_t)sidx * C + q * VE), f);
+        }
+        const int a = live ? s_soff[slot] : 0, b = live ? s_soff[slot + 1] : 0;
+        for (int i = a; i < b; ++i) {
+            const int t = s_list[i];
+            const int p = t / K;
+            const int px = bp.x0 + (p & 7), py = bp.y0 + (p >> 3);
+            float gv[VE];
+            if (has_vec) {
+                const float* src = grad_feat + (cam.pixel_offset + (int64_t)py * cam.width + px) * C + q * VE;
+#pragma unroll
+                for (int e = 0; e < VE; e += 4) {
+                    const float4 v = *reinterpret_cast<const float4*>(src + e);
+                    gv[e] = v.x;
+                    gv[e + 1] = v.y;
+                    gv[e + 2] = v.z;
+                    gv[e + 3] = v.w;
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < VE; ++e) gv[e] = 0.f;
+            }
+            const float w = __uint_as_float(s_pairs[t].y);
+            float part = 0.f;
+#pragma unroll
+            for (int e = 0; e < VE; ++e) {
+                part = fmaf(gv[e], f[e], part);
+                acc[e] = fmaf(w, gv[e], acc[e]);
+            }
+#pragma unroll
+            for (int d = 1; d < TPP; d <<= 1) part += __shfl_xor(part, d, 64);
+            if (q == 0) s_D[t] = part;
+        }
+        if (live && has_vec) {
+#pragma unroll
+            for (int e = 0; e < VE; ++e) atomicAdd(&grad_feats[(int64_t)sidx * C + q * VE + e], acc[e]);
+        }
+    }
+    for (int t = tid; t < kGradSlots * 10; t += kGradThreads) (&s_grec[0][0])[t] = 0.f;
+    // 2. per contribution, all pairs of the block in parallel: (a) alpha (the
+    //    forward's float value); (b) per pixel, from LDS only, the transmittance
+    //    before every contribution (the forward's double-precision product) and
+    //    the suffix sums; (c) the chain to dL/dL and dL/do, summed per row slot.
+    for (int t = tid; t < npairs; t += kGradThreads) {
+        const int p = t / K, j = t - p * K;
+        if (j >= s_cnt[p]) continue;
+        const int px = bp.x0 + (p & 7), py = bp.y0 + (p >> 3);
+        const FsRecord& r = records[(int64_t)bp.view * n + rowlist[s_pairs[t].x]];
+        const FsResp rs = fs_response(r, (double)(px - r.ax), (double)(py - r.ay));
+        const float Gs = __builtin_amdgcn_exp2f(-0.72134752044448170f * (float)rs.d2);
+        s_S[t] = fminf(o.alpha_max, r.o * Gs);   // alpha, for now
+    }
+    __syncthreads();
+    if (tid < 64) {
+        const int p = tid;
+        const int c = s_cnt[p];
+        double T = 1.0;
+        for (int j = 0; j < c; ++j) {
+            const float al = s_S[p * K + j];
+            s_S[p * K + j] = (float)T;   // transmittance before the contribution
+            s_T2[p * K + j] = al;
+            T = T * (1.0 - (double)al);
+        }
+        float suffix = 0.f;
+        for (int j = c - 1; j >= 0; --j) {
+            const float wD = __uint_as_float(s_pairs[p * K + j].y) * s_D[p * K + j];
+            s_U[p * K + j] = suffix;
+            suffix += wD;
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < npairs; t += kGradThreads) {
+        const int p = t / K, j = t - p * K;
+        if (j >= s_cnt[p]) continue;
+        const int px = bp.x0 + (p & 7), py = bp.y0 + (p >> 3);
+        const uint32_t slot = s_pairs[t].x;
+        const int64_t rid = (int64_t)bp.view * n + rowlist[slot];
+        const FsRecord& r = records[rid];
+        const double ddx = (double)(px - r.ax), ddy = (double)(py - r.ay);
+        const FsResp rs = fs_response(r, ddx, ddy);
+        const float Gs = __builtin_amdgcn_exp2f(-0.72134752044448170f * (float)rs.d2);
+        const bool clamped = r.o * Gs > o.alpha_max;
+        if (clamped) continue;
+        const float alpha = s_T2[t];
+        const float dalpha = s_S[t] * s_D[t] - s_U[t] / (1.f - alpha);
+        float gg[10];
+        blend_chain(r, rs, ddx, ddy, Gs, dalpha, gg);
+        if (slot < (uint32_t)kGradSlots) {
+#pragma unroll
+            for (int k = 0; k < 10; ++k) atomicAdd(&s_grec[slot][k], gg[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 10; ++k) atomicAdd(&grad_records[rid * kGradFloats + k], gg[k]);
+        }
+    }
+    __syncthreads();
+    const int nslot = (int)(R < (uint32_t)kGradSlots ? R : (uint32_t)kGradSlots);
+    for (int t = tid; t < nslot * 10; t += kGradThreads) {
+        const int slot = t / 10, k = t - slot * 10;
+        const float v = s_grec[slot][k];
+        if (v != 0.f) atomicAdd(&grad_records[((int64_t)bp.view * n + rowlist[slot]) * kGradFloats + k], v);
+    }
+}
+
+template <typename FT>
+hipError_t launch_topk_grad(const FsRecord* records, const void* feats, int C, int64_t n, const fs_camera* cams,
+                            int num_views, int64_t nblocks, const fs_opts& o, const float* grad_feat,
+                            float* grad_records, float* grad_feats, const FsWorkspace& ws, hipStream_t s) {
+    constexpr int VE = RowV<FT>::VE;
+    const int nv = C / VE;
+    int tpp = 4;
+    while (tpp < nv) tpp <<= 1;
+    const FT* f = static_cast<const FT*>(feats);
+#define FS_GRAD(TPP)                                                                                             \
+    hipLaunchKernelGGL((topk_grad_kernel<FT, TPP>), dim3((unsigned)nblocks), dim3(kGradThreads), 0, s, records,    \
+                       ws.topk_pairs, ws.topk_counts, ws.topk_rows, ws.topk_nrows, f, C, o.topk, n, cams, num_views, \
+                       o.tile, nblocks, o, grad_feat, grad_records, grad_feats)
+    switch (tpp) {
+        case 4: FS_GRAD(4); break;
+        case 8: FS_GRAD(8); break;
+        case 16: FS_GRAD(16); break;
+        case 32: FS_GRAD(32); break;
+        default: FS_GRAD(64); break;
+    }
+#undef FS_GRAD
+    return hipGetLastError();
+}
+
 template <int CPL, typename FT>
 hipError_t launch_bwd(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges, const void* feats,
                       int C, int64_t n, const fs_camera* cams, int num_views, int64_t total_tiles, const fs_opts& o,
@@ -364,7 +647,6 @@ hipError_t fs_launch_render_backward(const float* means, const float* scales, co
                                      float* grad_scales, float* grad_quats, float* grad_opacity, float* grad_feats,
                                      const FsWorkspace& ws, hipStream_t s) {
     (void)out_n;
-    (void)ws;
     const int64_t nrec = n * num_views * kGradFloats;
     {
         unsigned blocks = (unsigned)((nrec + 255) / 256);
@@ -373,7 +655,20 @@ hipError_t fs_launch_render_backward(const float* means, const float* scales, co
     }
     hipError_t e;
     const bool bf16 = o.feat_dtype == FS_FEAT_BF16;
-    if (C <= 64)
+    const int ve = bf16 ? 8 : 4;
+    const int sb = o.tile / 8;
+    const int64_t nblocks = total_tiles * sb * sb;
+    if (o.topk > 0 && o.topk <= kGradMaxK && C % ve == 0 && C / ve <= 64 && ws.topk_pairs != nullptr &&
+        ws.topk_counts != nullptr && nblocks < (int64_t(1) << 31)) {
+        // recompute the selection, then the per-block gradient pass
+        e = fs_launch_topk_select(records, vals, ranges, n, cams, num_views, total_tiles, o, nullptr, ws.topk_counts,
+                                  nullptr, nullptr, nullptr, ws, s);
+        if (e != hipSuccess) return e;
+        e = bf16 ? launch_topk_grad<uint16_t>(records, feats, C, n, cams, num_views, nblocks, o, grad_feat,
+                                              grad_records, grad_feats, ws, s)
+                 : launch_topk_grad<float>(records, feats, C, n, cams, num_views, nblocks, o, grad_feat, grad_records,
+                                           grad_feats, ws, s);
+    } else if (C <= 64)
         e = bf16 ? launch_bwd<1, uint16_t>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o, out_T,
                                            out_last, grad_feat, grad_records, grad_feats, s)
                  : launch_bwd<1, float>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o, out_T,

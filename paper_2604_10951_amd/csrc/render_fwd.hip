@@ -171,7 +171,7 @@ FS_DEV void render_block(int64_t block, FwdShared<CPL, FT, WAVES, BG>& sm, const
                 if (r.x1 < wx0 || r.x0 > wx0 + 7 || r.y1 < wy0 || r.y0 > wy0 + 7) continue;
                 if (!done) {
                     const FsResp rs = fs_response(r, (double)(px - r.ax), (double)(py - r.ay));
-                    if (rs.d2 <= r.k2) {
+                    if (rs.d2 <= r.k2 && fs_in_box(r, px, py)) {
                         const float G = __builtin_amdgcn_exp2f(neg_half_log2e * (float)rs.d2);
                         const float alpha = fminf(o.alpha_max, r.o * G);
                         const double Tn = T * (1.0 - (double)alpha);

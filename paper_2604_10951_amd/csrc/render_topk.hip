@@ -25,24 +25,19 @@
 namespace {
 
 constexpr int kSelBatch = 32;   // list entries staged per step in the selection pass
-constexpr int kSub = 8;         // entries whose responses are evaluated together
 constexpr int kGatherThreads = 256;
 constexpr int kGatherUnroll = 8;  // (surfel, weight) pairs whose row loads are in flight together
 constexpr int kStagedK = 16;      // largest K of the staged gather (its lists live in LDS)
 
-// Workgroup -> work item: dispatch hands workgroup g to XCD g mod 8; remap so
-// that XCD x takes the contiguous run [x * per, (x + 1) * per).  The last
-// G mod 8 workgroups keep their own index.
-FS_DEV int64_t xcd_remap(int64_t g, int64_t G) {
-    const int64_t per = G / 8;
-    if (g >= per * 8) return g;
-    return (g % 8) * per + g / 8;
-}
 
 struct SelShared {
     FsRecord rec[kSelBatch];
     uint32_t recid[kSelBatch];
     uint32_t sidx[kSelBatch];
+    int pre[kSelBatch];            // exclusive prefix of the entries' box pixel counts in the block
+    int box[kSelBatch];            // x0 | y0 << 8 | width << 16 of the entry's box inside the block (block-local)
+    uint32_t mask[64];             // per pixel: entries of the batch it accepts
+    float alpha[kSelBatch][64];    // alpha, then the blend weight, per (entry, pixel)
 };
 
 __global__ void __launch_bounds__(64)
@@ -136,64 +131,97 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
             fetch_vals(b0 + 2 * BG, nxt_rid);
         }
         walked += (uint32_t)nb;
-        for (int e0 = 0; e0 < nb; e0 += kSub) {
-            // (a) responses of kSub entries: independent of each other and of
-            //     the transmittance, and computed without branches (box, stop
-            //     and accept tests become mask bits), so their FP64 chains and
-            //     LDS reads overlap
-            float al[kSub];
-            uint32_t hit = 0u;
-#pragma unroll
-            for (int u = 0; u < kSub; ++u) {
-                const int e = e0 + u < nb ? e0 + u : nb - 1;
-                const FsRecord r = sm.rec[e];   // whole record in registers: one basic block, no waits between fields
-                const bool box = (r.x1 >= bp.x0) & (r.x0 <= bp.x0 + 7) & (r.y1 >= bp.y0) & (r.y0 <= bp.y0 + 7);
-                const FsResp rs = fs_response(r, (double)(px - r.ax), (double)(py - r.ay));
-                const float G = __builtin_amdgcn_exp2f(neg_half_log2e * (float)rs.d2);
-                al[u] = fminf(o.alpha_max, r.o * G);
-                hit |= (uint32_t)(box & (e0 + u < nb) & (rs.d2 <= r.k2)) << u;
+        // (a) responses, compacted to the footprints: every entry's pixel box
+        //     is clipped to the block, the (entry, pixel) pairs of the batch
+        //     are numbered consecutively and one lane evaluates one pair, so
+        //     the FP64 work follows the footprints' area, not 64 pixels per
+        //     entry.  Accepted pairs leave alpha and a mask bit in LDS.
+        int ecount = 0, ebox = 0;
+        if (lane < nb) {
+            const FsRecord& r = sm.rec[lane];
+            const int x0 = max((int)r.x0, bp.x0), x1 = min((int)r.x1, bp.x0 + 7);
+            const int y0 = max((int)r.y0, bp.y0), y1 = min((int)r.y1, bp.y0 + 7);
+            if (x0 <= x1 && y0 <= y1) {
+                ecount = (x1 - x0 + 1) * (y1 - y0 + 1);
+                ebox = (x0 - bp.x0) | ((y0 - bp.y0) << 8) | ((x1 - x0 + 1) << 16);
             }
-            if (done) hit = 0u;
-            // (b) front-to-back transmittance over the accepted entries
-            float wv[kSub];
-            uint32_t bm = 0u;   // entries of this sub-batch the lane blends
-            const int c_start = cnt;
-#pragma unroll
-            for (int u = 0; u < kSub; ++u) {
-                wv[u] = 0.f;
-                if (((hit >> u) & 1u) && !done) {
-                    const double Tn = T * (1.0 - (double)al[u]);
-                    if (Tn < t_stop) {
-                        done = true;
-                    } else {
-                        wv[u] = (float)((double)al[u] * T);
-                        bm |= 1u << u;
-                        T = Tn;
-                        ++cnt;
-                        last = (int)(b0 + e0 + u);
-                        if (cnt == K) done = true;
-                    }
-                }
-            }
-            // (c) row slots: the entries any pixel of the block blends get
-            //     consecutive slots of the block's row list, in list order
-            uint32_t used = 0u;
-#pragma unroll
-            for (int u = 0; u < kSub; ++u) used |= (__ballot((bm >> u) & 1u) != 0ull ? 1u : 0u) << u;
-#pragma unroll
-            for (int u = 0; u < kSub; ++u) {
-                if ((bm >> u) & 1u) {
-                    const int j = c_start + __popc(bm & ((1u << u) - 1u));
-                    const uint32_t slot = nslots + (uint32_t)__popc(used & ((1u << u) - 1u));
-                    mine[j] = make_uint2(slot, __float_as_uint(wv[u]));
-                    if (out_idx) out_idx[pix * K + j] = (int32_t)sm.recid[e0 + u];
-                }
-            }
-            if (lane < kSub && ((used >> lane) & 1u))
-                rowlist[nslots + (uint32_t)__popc(used & ((1u << lane) - 1u))] = sm.sidx[e0 + lane];
-            nslots += (uint32_t)__popc(used);
-            if (__all(done)) break;
         }
+        int incl = ecount;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += y;
+        }
+        const int total = __shfl(incl, 63, 64);
+        if (lane < BG) {
+            sm.pre[lane] = lane < nb ? incl - ecount : total;
+            sm.box[lane] = ebox;
+        }
+        sm.mask[lane] = 0u;
+        __syncthreads();
+        for (int k0 = 0; k0 < total; k0 += 64) {
+            const int k = k0 + lane;
+            if (k < total) {
+                int e = 0;   // the entry owning pair k: last e with pre[e] <= k
+#pragma unroll
+                for (int step = BG / 2; step > 0; step >>= 1)
+                    if (sm.pre[e + step] <= k) e += step;
+                const int m = k - sm.pre[e];
+                const int b = sm.box[e];
+                const int w = b >> 16;
+                const int lx = (b & 0xff) + m % w, ly = ((b >> 8) & 0xff) + m / w;
+                const FsRecord& r = sm.rec[e];
+                const FsResp rs = fs_response(r, (double)(bp.x0 + lx - r.ax), (double)(bp.y0 + ly - r.ay));
+                if (rs.d2 <= r.k2) {
+                    const float G = __builtin_amdgcn_exp2f(neg_half_log2e * (float)rs.d2);
+                    const int p = ly * 8 + lx;
+                    sm.alpha[e][p] = fminf(o.alpha_max, r.o * G);
+                    atomicOr(&sm.mask[p], 1u << e);
+                }
+            }
+        }
+        __syncthreads();
+        // (b) lane = pixel: front-to-back transmittance over its accepted
+        //     entries; blended ones keep their weight in LDS
+        uint32_t hit = done ? 0u : sm.mask[lane];
+        uint32_t bm = 0u;
+        const int c_start = cnt;
+        while (hit != 0u && !done) {
+            const int e = __builtin_ctz(hit);
+            hit &= hit - 1u;
+            const float al = sm.alpha[e][lane];
+            const double Tn = T * (1.0 - (double)al);
+            if (Tn < t_stop) {
+                done = true;
+            } else {
+                sm.alpha[e][lane] = (float)((double)al * T);
+                bm |= 1u << e;
+                T = Tn;
+                ++cnt;
+                last = (int)(b0 + e);
+                if (cnt == K) done = true;
+            }
+        }
+        // (c) row slots: the entries any pixel of the block blends get
+        //     consecutive slots of the block's row list, in list order
+        uint32_t used = bm;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) used |= __shfl_xor(used, d, 64);
+        {
+            uint32_t mm = bm;
+            int j = c_start;
+            while (mm != 0u) {
+                const int e = __builtin_ctz(mm);
+                mm &= mm - 1u;
+                const uint32_t slot = nslots + (uint32_t)__popc(used & ((1u << e) - 1u));
+                mine[j] = make_uint2(slot, __float_as_uint(sm.alpha[e][lane]));
+                if (out_idx) out_idx[pix * K + j] = (int32_t)sm.recid[e];
+                ++j;
+            }
+        }
+        if (lane < BG && ((used >> lane) & 1u))
+            rowlist[nslots + (uint32_t)__popc(used & ((1u << lane) - 1u))] = sm.sidx[lane];
+        nslots += (uint32_t)__popc(used);
         if (__all(done)) break;
     }
 
@@ -210,7 +238,7 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
     }
     if (lane == 0) nrows[block] = nslots;
     if (inside) {
-        out_T[pix] = (float)T;
+        if (out_T) out_T[pix] = (float)T;
         out_n[pix] = cnt;
         if (out_last) out_last[pix] = last;
         if (out_idx)
@@ -251,15 +279,19 @@ struct Vec<uint16_t, 1> {
 };
 
 // Store VE accumulated channels at dst[c0 ...] (c0 + VE <= C for vectors).
+// The feature image is written once and not read back by this pass:
+// non-temporal stores stream it out without evicting the feature rows that
+// neighbouring blocks still read from L2.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <int VE>
 FS_DEV void store_vec(float* __restrict__ dst, int c0, const float* acc) {
     if constexpr (VE == 4) {
-        *reinterpret_cast<float4*>(dst + c0) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+        __builtin_nontemporal_store(f32x4{acc[0], acc[1], acc[2], acc[3]}, reinterpret_cast<f32x4*>(dst + c0));
     } else if constexpr (VE == 8) {
-        *reinterpret_cast<float4*>(dst + c0) = make_float4(acc[0], acc[1], acc[2], acc[3]);
-        *reinterpret_cast<float4*>(dst + c0 + 4) = make_float4(acc[4], acc[5], acc[6], acc[7]);
+        __builtin_nontemporal_store(f32x4{acc[0], acc[1], acc[2], acc[3]}, reinterpret_cast<f32x4*>(dst + c0));
+        __builtin_nontemporal_store(f32x4{acc[4], acc[5], acc[6], acc[7]}, reinterpret_cast<f32x4*>(dst + c0 + 4));
     } else {
-        dst[c0] = acc[0];
+        __builtin_nontemporal_store(acc[0], dst + c0);
     }
 }
 
@@ -464,6 +496,23 @@ hipError_t launch_gather(const uint2* pairs, const int32_t* counts, const uint32
 
 }  // namespace
 
+hipError_t fs_launch_topk_select(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges, int64_t n,
+                                 const fs_camera* cams, int num_views, int64_t total_tiles, const fs_opts& o,
+                                 float* out_T, int32_t* out_n, int32_t* out_last, int32_t* out_idx,
+                                 uint64_t* counters, const FsWorkspace& ws, hipStream_t s) {
+    const int sb = o.tile / 8;
+    const int64_t nblocks = total_tiles * sb * sb;
+    if (ws.topk_pairs == nullptr || ws.topk_rows == nullptr || ws.topk_nrows == nullptr ||
+        ws.topk_pair_slots < nblocks * 64 * (int64_t)o.topk || nblocks >= (int64_t(1) << 31))
+        return hipErrorInvalidValue;
+    hipError_t e = fs_launch_block_order(ranges, sb * sb, (uint32_t)nblocks, ws, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(topk_select_kernel, dim3((unsigned)nblocks), dim3(64), 0, s, records, vals, ranges,
+                       (uint32_t)n, n * num_views, cams, num_views, o.tile, o, nblocks, ws.render_order,
+                       ws.topk_pairs, ws.topk_rows, ws.topk_nrows, out_T, out_n, out_last, out_idx, counters);
+    return hipGetLastError();
+}
+
 hipError_t fs_launch_render_topk_split(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges,
                                        const void* feats, int C, int64_t n, const fs_camera* cams, int num_views,
                                        int64_t total_tiles, const fs_opts& o, float* out_feat, float* out_T,
@@ -476,12 +525,8 @@ hipError_t fs_launch_render_topk_split(const FsRecord* records, const uint32_t* 
         ws.topk_pair_slots < nblocks * 64 * (int64_t)o.topk ||
         nblocks >= (int64_t(1) << 31))
         return hipErrorInvalidValue;
-    hipError_t e = fs_launch_block_order(ranges, sb * sb, (uint32_t)nblocks, ws, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(topk_select_kernel, dim3((unsigned)nblocks), dim3(64), 0, s, records, vals, ranges,
-                       (uint32_t)n, n * num_views, cams, num_views, o.tile, o, nblocks, ws.render_order,
-                       ws.topk_pairs, ws.topk_rows, ws.topk_nrows, out_T, out_n, out_last, out_idx, counters);
-    e = hipGetLastError();
+    hipError_t e = fs_launch_topk_select(records, vals, ranges, n, cams, num_views, total_tiles, o, out_T, out_n,
+                                         out_last, out_idx, counters, ws, s);
     if (e != hipSuccess) return e;
     const bool bf16 = o.feat_dtype == FS_FEAT_BF16;
     if (bf16)
