@@ -187,7 +187,7 @@ def measured_traffic(schedule):
     FETCH_SIZE / WRITE_SIZE counter runs, if the render sources are unchanged
     since and the runs used this schedule."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "render_fwd_topk_headline_traffic.json")
+    path = os.path.join(ROOT, "profiles", "render_topk_headline_traffic.json")
     try:
         rec = json.load(open(path))
         if rec.get("schedule", "grid") != schedule:
@@ -207,19 +207,26 @@ def frame_bytes(n, P, counters, H, W, C, feat_bytes=4):
     return 40 * n + 96 * n + (12 + 24 + 100) * P + counters["rows"] * C * feat_bytes + H * W * (4 * C + 8)
 
 
-def cpu_baseline(scene, cam):
+def cpu_baseline(scene, cam, min_seconds=10.0):
+    """The oracle's whole frame (projection + per-pixel candidate lists +
+    blend), repeated until about min_seconds of CPU time have passed."""
     import oracle
+    frames = 0
     t0 = time.perf_counter()
-    proj = oracle.project_scene(scene, cam)
-    oracle.render_image(proj, scene.opacity, scene.feats, cam.width, cam.height, K=K)
-    dt = time.perf_counter() - t0
+    while True:
+        proj = oracle.project_scene(scene, cam)
+        oracle.render_image(proj, scene.opacity, scene.feats, cam.width, cam.height, K=K)
+        frames += 1
+        if time.perf_counter() - t0 >= min_seconds:
+            break
+    dt = (time.perf_counter() - t0) / frames
     cores = len(os.sched_getaffinity(0))
     omp = os.environ.get("OMP_NUM_THREADS")
     if omp:
         cores = min(cores, int(omp))
     return {"value": 1.0 / dt, "unit": "FPS", "cores": cores, "kind": "oracle",
-            "sample": f"one whole frame of the same workload (K={K}): projection + per-pixel candidate lists + "
-                      f"blend, FP64, {dt:.2f} s"}
+            "sample": f"{frames} whole frames of the same workload (K={K}): projection + per-pixel candidate "
+                      f"lists + blend, FP64, {dt:.2f} s per frame"}
 
 
 def main():
@@ -233,6 +240,8 @@ def main():
     ap.add_argument("--schedule", default="split", choices=("grid", "persistent", "split"),
                     help="render schedule of the Top-K frames (the full blend uses 'grid')")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 / batched / backward forms")
+    ap.add_argument("--form", choices=("batched", "backward", "bf16"), default=None,
+                    help="run only this form and print its JSON line (profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -241,6 +250,17 @@ def main():
                                    "(views or screen regions per GPU), not measured here"}))
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if args.form is not None:
+        fs, fw = 10, 2
+        if args.form == "backward":
+            res = form_backward(dev, fs, fw)
+        elif args.form == "bf16":
+            res = form_bf16(dev, fs, fw)
+        else:
+            scene, _ = scenes.headline(seed=args.seed, channels=C)
+            res = form_batched(raster.scene_tensors(scene, dev), dev, fs, fw)
+        print(json.dumps({"form": args.form, **res}), flush=True)
+        return
     if args.calibrate_copy:
         src = torch.ones(args.calibrate_copy << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
