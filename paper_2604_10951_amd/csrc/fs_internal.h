@@ -157,6 +157,25 @@ FS_DEV bool fs_project(const float* pm, const float* ps, const float* pq, float 
 
 // The footprint predicate at pixel (px, py): u^2 + v^2 <= k^2 with
 // (u, v) = (h0 / h2, h1 / h2), h = H (px + .5, py + .5, 1).
+// 1/x and sqrt(x) (x >= 0) to ~1e-15 relative: hardware seeds plus Newton
+// steps (each step doubles the bits of the ~2^-23 seeds).
+FS_DEV double fs_rcp_approx(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
+FS_DEV double fs_sqrt_approx(double x) {
+    if (!(x > 0.0)) return 0.0;
+    double y = __builtin_amdgcn_rsq(x);      // 1 / sqrt(x)
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    double r = x * y;                        // sqrt(x)
+    r = fma(0.5 * y, fma(-r, r, x), r);      // one Newton step on r
+    return r;
+}
+
 FS_DEV bool fs_pixel_in(const double H[9], double k2, int px, int py) {
     const double x = (double)px + 0.5, y = (double)py + 0.5;
     const double h0 = (H[0] * x + H[1] * y) + H[2];
@@ -309,17 +328,21 @@ FS_DEV bool fs_line_interval(const FsFootprint& fp, bool rows, int l, int lo_lim
         while (hi < hi_lim && pin(hi + 1)) ++hi;
         return true;
     }
-    const double sq = sqrt(disc);
+    // The roots only locate the interval: every centre within eps of a root
+    // is re-decided below with the exact predicate, so they need ~1e-15
+    // relative accuracy, not correct rounding -- hardware reciprocal and
+    // reciprocal square root seeds refined by Newton steps.
+    const double sq = fs_sqrt_approx(disc);
     // roots s1 <= s2 (numerically stable form)
     double s1, s2;
     if (b >= 0.0) {
         const double t = -(b + sq);
-        s1 = t / a;
-        s2 = (t != 0.0) ? c / t : 0.0;
+        s1 = t * fs_rcp_approx(a);
+        s2 = (t != 0.0) ? c * fs_rcp_approx(t) : 0.0;
     } else {
         const double t = -b + sq;
-        s2 = t / a;
-        s1 = c / t;
+        s2 = t * fs_rcp_approx(a);
+        s1 = c * fs_rcp_approx(t);
     }
     if (s1 > s2) {
         const double tmp = s1;

@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(64)
 topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restrict__ vals,
                    const uint32_t* __restrict__ ranges, uint32_t n, int64_t num_records,
                    const fs_camera* __restrict__ cams, int num_views, int S, fs_opts o, int64_t nblocks,
-                   const uint32_t* __restrict__ order, uint2* __restrict__ pairs, uint32_t* __restrict__ rows,
+                   uint2* __restrict__ pairs, uint32_t* __restrict__ rows,
                    uint32_t* __restrict__ nrows, float* __restrict__ out_T, int32_t* __restrict__ out_n,
                    int32_t* __restrict__ out_last, int32_t* __restrict__ out_idx, uint64_t* __restrict__ counters) {
     constexpr int BG = kSelBatch;
@@ -52,8 +52,7 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
     constexpr int kRecSlots = (BG * kQ + 63) / 64;    // record float4 per lane
     __shared__ SelShared sm;
     const int lane = threadIdx.x;
-    // longest tile lists are dispatched first, so the longest walks overlap the rest
-    const int64_t block = order[blockIdx.x];
+    const int64_t block = xcd_remap(blockIdx.x, nblocks);
     const BlockPos bp = locate_block(block, S, 8, cams, num_views);
     if (!bp.valid) return;   // uniform across the wave
     const fs_camera& cam = cams[bp.view];
@@ -472,7 +471,7 @@ hipError_t launch_gather(const uint2* pairs, const int32_t* counts, const uint32
             case 4: FS_GATHER_LDS(4, 64); break;
             case 8: FS_GATHER_LDS(8, 64); break;
             case 16: FS_GATHER_LDS(16, 64); break;
-            case 32: FS_GATHER_LDS(32, 48); break;
+            case 32: FS_GATHER_LDS(32, 24); break;
             default: FS_GATHER_LDS(64, 24); break;
         }
 #undef FS_GATHER_LDS
@@ -505,10 +504,8 @@ hipError_t fs_launch_topk_select(const FsRecord* records, const uint32_t* vals, 
     if (ws.topk_pairs == nullptr || ws.topk_rows == nullptr || ws.topk_nrows == nullptr ||
         ws.topk_pair_slots < nblocks * 64 * (int64_t)o.topk || nblocks >= (int64_t(1) << 31))
         return hipErrorInvalidValue;
-    hipError_t e = fs_launch_block_order(ranges, sb * sb, (uint32_t)nblocks, ws, s);
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(topk_select_kernel, dim3((unsigned)nblocks), dim3(64), 0, s, records, vals, ranges,
-                       (uint32_t)n, n * num_views, cams, num_views, o.tile, o, nblocks, ws.render_order,
+                       (uint32_t)n, n * num_views, cams, num_views, o.tile, o, nblocks,
                        ws.topk_pairs, ws.topk_rows, ws.topk_nrows, out_T, out_n, out_last, out_idx, counters);
     return hipGetLastError();
 }

@@ -6,8 +6,8 @@
 // the 64-bit key gives, since a record is emitted at most once per tile and
 // records are emitted in increasing order.  It is produced in two steps that
 // suit a list split into many short per-tile runs:
-//   1. a counting sort by tile: per-tile counts (LDS histograms per chunk of
-//      pairs), one exclusive scan that also yields every tile's [start, end)
+//   1. a counting sort by tile: per-tile counts (LDS histograms per 8192-pair
+//      chunk), one exclusive scan that also yields every tile's [start, end)
 //      range, and a scatter that places each pair at its tile's start plus a
 //      cursor (any order inside the tile);
 //   2. a sort of every tile's run by (depth key, record), as 64-bit composite
@@ -22,10 +22,11 @@
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kWaveCap = 256;     // entries per run sorted by one wave (2 KB of LDS per wave)
+constexpr int kWaveCap = 512;     // entries per run sorted by one wave (4 KB of LDS per wave)
 constexpr int kLargeCap = 8192;   // entries per run sorted in LDS by a workgroup (64 KB)
 constexpr int kLdsTiles = 16384;  // tile counts kept in LDS by the count and scatter kernels
-constexpr int kChunk = 2048;      // pairs per workgroup in the count and scatter kernels
+constexpr int kChunk = 8192;      // pairs per workgroup in the count and scatter kernels
+constexpr int kChunkThreads = 1024;
 constexpr int kLongGrid = 512;    // workgroups working through the long-run list
 constexpr int kLongThreads = 1024;
 constexpr int kScanItems = 4;
@@ -55,30 +56,30 @@ __global__ void sort_clear_kernel(uint32_t* __restrict__ cnt, uint32_t* __restri
 // the global counts, so a tile with many pairs costs one global atomic per
 // workgroup, not one per pair; with more tiles, pairs are counted with
 // global atomics.
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kChunkThreads)
 sort_count_kernel(const uint64_t* __restrict__ keys, const int64_t* __restrict__ num_pairs, int64_t capacity,
                   int64_t tiles, uint32_t* __restrict__ cnt) {
     __shared__ uint32_t h[kLdsTiles];
     const int64_t P = load_count(num_pairs, capacity);
     if (tiles > kLdsTiles) {
-        const int64_t stride = (int64_t)gridDim.x * kThreads;
-        for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < P; i += stride) {
+        const int64_t stride = (int64_t)gridDim.x * kChunkThreads;
+        for (int64_t i = (int64_t)blockIdx.x * kChunkThreads + threadIdx.x; i < P; i += stride) {
             const uint64_t t = keys[i] >> 32;
             if (t < (uint64_t)tiles) atomicAdd(&cnt[t], 1u);
         }
         return;
     }
     const int T = (int)tiles;
-    for (int i = threadIdx.x; i < T; i += kThreads) h[i] = 0;
+    for (int i = threadIdx.x; i < T; i += kChunkThreads) h[i] = 0;
     __syncthreads();
     const int64_t c0 = (int64_t)blockIdx.x * kChunk;
     const int64_t c1 = c0 + kChunk < P ? c0 + kChunk : P;
-    for (int64_t i = c0 + threadIdx.x; i < c1; i += kThreads) {
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += kChunkThreads) {
         const uint64_t t = keys[i] >> 32;
         if (t < (uint64_t)tiles) atomicAdd(&h[t], 1u);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < T; i += kThreads)
+    for (int i = threadIdx.x; i < T; i += kChunkThreads)
         if (h[i]) atomicAdd(&cnt[i], h[i]);
 }
 
@@ -173,15 +174,15 @@ sort_scan_kernel(const uint32_t* __restrict__ cnt, int64_t tiles, uint32_t* __re
 // With at most kLdsTiles tiles every workgroup reserves, per tile, one run of
 // positions for its whole chunk (one global atomic per tile it touches) and
 // hands them out with LDS cursors; otherwise every pair takes a global atomic.
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kChunkThreads)
 sort_scatter_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
                     const int64_t* __restrict__ num_pairs, int64_t capacity, int64_t tiles,
                     const uint32_t* __restrict__ ranges, uint32_t* __restrict__ fill, uint2* __restrict__ out) {
     __shared__ uint32_t h[kLdsTiles];
     const int64_t P = load_count(num_pairs, capacity);
     if (tiles > kLdsTiles) {
-        const int64_t stride = (int64_t)gridDim.x * kThreads;
-        for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < P; i += stride) {
+        const int64_t stride = (int64_t)gridDim.x * kChunkThreads;
+        for (int64_t i = (int64_t)blockIdx.x * kChunkThreads + threadIdx.x; i < P; i += stride) {
             const uint64_t k = keys[i];
             const uint64_t t = k >> 32;
             if (t < (uint64_t)tiles) {
@@ -192,19 +193,19 @@ sort_scatter_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restric
         return;
     }
     const int T = (int)tiles;
-    for (int i = threadIdx.x; i < T; i += kThreads) h[i] = 0;
+    for (int i = threadIdx.x; i < T; i += kChunkThreads) h[i] = 0;
     __syncthreads();
     const int64_t c0 = (int64_t)blockIdx.x * kChunk;
     const int64_t c1 = c0 + kChunk < P ? c0 + kChunk : P;
-    for (int64_t i = c0 + threadIdx.x; i < c1; i += kThreads) {
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += kChunkThreads) {
         const uint64_t t = keys[i] >> 32;
         if (t < (uint64_t)tiles) atomicAdd(&h[t], 1u);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < T; i += kThreads)
+    for (int i = threadIdx.x; i < T; i += kChunkThreads)
         if (h[i]) h[i] = ranges[2 * i] + atomicAdd(&fill[i], h[i]);   // first position of this chunk's run
     __syncthreads();
-    for (int64_t i = c0 + threadIdx.x; i < c1; i += kThreads) {
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += kChunkThreads) {
         const uint64_t k = keys[i];
         const uint64_t t = k >> 32;
         if (t < (uint64_t)tiles) {
@@ -430,14 +431,14 @@ hipError_t fs_launch_sort(uint64_t* keys, uint32_t* vals, int64_t capacity, cons
         if (chunks >= (int64_t(1) << 31)) return hipErrorInvalidValue;
         pblocks = (unsigned)(chunks < 1 ? 1 : chunks);
     } else {
-        const int64_t b = (pmax + kThreads * 4 - 1) / (kThreads * 4);
-        pblocks = (unsigned)(b < 1 ? 1 : (b > 2048 ? 2048 : b));
+        const int64_t b = (pmax + kChunkThreads * 4 - 1) / (kChunkThreads * 4);
+        pblocks = (unsigned)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
     }
-    hipLaunchKernelGGL(sort_count_kernel, dim3(pblocks), dim3(kThreads), 0, s, keys, num_pairs, capacity, total_tiles,
-                       ws.tile_cnt);
+    hipLaunchKernelGGL(sort_count_kernel, dim3(pblocks), dim3(kChunkThreads), 0, s, keys, num_pairs, capacity,
+                       total_tiles, ws.tile_cnt);
     hipLaunchKernelGGL(sort_scan_kernel, dim3((unsigned)parts), dim3(kThreads), 0, s, ws.tile_cnt, total_tiles, ranges,
                        ws.sort_status, ws.sort_ticket, parts);
-    hipLaunchKernelGGL(sort_scatter_kernel, dim3(pblocks), dim3(kThreads), 0, s, keys, vals, num_pairs, capacity,
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3(pblocks), dim3(kChunkThreads), 0, s, keys, vals, num_pairs, capacity,
                        total_tiles, ranges, ws.tile_fill, ws.runs);
     const unsigned sblocks = (unsigned)((total_tiles + kThreads / 64 - 1) / (kThreads / 64));
     hipLaunchKernelGGL(sort_short_runs_kernel, dim3(sblocks), dim3(kThreads), 0, s, ws.runs, ranges, total_tiles, keys,
