@@ -34,10 +34,9 @@ struct SelShared {
     FsRecord rec[kSelBatch];
     uint32_t recid[kSelBatch];
     uint32_t sidx[kSelBatch];
-    int pre[kSelBatch];            // exclusive prefix of the entries' box pixel counts in the block
-    int box[kSelBatch];            // x0 | y0 << 8 | width << 16 of the entry's box inside the block (block-local)
+    int pre[kSelBatch];            // exclusive prefix of the entries' pair counts
+    uint64_t pixels[kSelBatch];    // per entry: pixels of the block inside its box that are still walking
     uint32_t mask[64];             // per pixel: entries of the batch it accepts
-    float alpha[kSelBatch][64];    // alpha, then the blend weight, per (entry, pixel)
 };
 
 __global__ void __launch_bounds__(64)
@@ -131,18 +130,24 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
         }
         walked += (uint32_t)nb;
         // (a) responses, compacted to the footprints: every entry's pixel box
-        //     is clipped to the block, the (entry, pixel) pairs of the batch
-        //     are numbered consecutively and one lane evaluates one pair, so
-        //     the FP64 work follows the footprints' area, not 64 pixels per
-        //     entry.  Accepted pairs leave alpha and a mask bit in LDS.
-        int ecount = 0, ebox = 0;
+        //     is clipped to the block and to the pixels still walking, the
+        //     (entry, pixel) pairs of the batch are numbered consecutively and
+        //     one lane evaluates one pair, so the FP64 work follows the
+        //     footprints' area over the active pixels, not 64 pixels per
+        //     entry.  Accepted pairs leave a mask bit in LDS.
+        const uint64_t walking = __ballot(!done);
+        int ecount = 0;
+        uint64_t epix = 0ull;
         if (lane < nb) {
             const FsRecord& r = sm.rec[lane];
             const int x0 = max((int)r.x0, bp.x0), x1 = min((int)r.x1, bp.x0 + 7);
             const int y0 = max((int)r.y0, bp.y0), y1 = min((int)r.y1, bp.y0 + 7);
             if (x0 <= x1 && y0 <= y1) {
-                ecount = (x1 - x0 + 1) * (y1 - y0 + 1);
-                ebox = (x0 - bp.x0) | ((y0 - bp.y0) << 8) | ((x1 - x0 + 1) << 16);
+                const uint64_t row = ((1ull << (x1 - x0 + 1)) - 1ull) << (x0 - bp.x0);   // bits of one pixel row
+                const int ny = y1 - y0 + 1;
+                const uint64_t rows = (ny == 8 ? ~0ull : ((1ull << (8 * ny)) - 1ull)) << (8 * (y0 - bp.y0));
+                epix = (row * 0x0101010101010101ull) & rows & walking;
+                ecount = __popcll(epix);
             }
         }
         int incl = ecount;
@@ -154,7 +159,7 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
         const int total = __shfl(incl, 63, 64);
         if (lane < BG) {
             sm.pre[lane] = lane < nb ? incl - ecount : total;
-            sm.box[lane] = ebox;
+            sm.pixels[lane] = epix;
         }
         sm.mask[lane] = 0u;
         __syncthreads();
@@ -165,35 +170,48 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
 #pragma unroll
                 for (int step = BG / 2; step > 0; step >>= 1)
                     if (sm.pre[e + step] <= k) e += step;
-                const int m = k - sm.pre[e];
-                const int b = sm.box[e];
-                const int w = b >> 16;
-                const int lx = (b & 0xff) + m % w, ly = ((b >> 8) & 0xff) + m / w;
+                // the m-th set bit of the entry's pixel mask
+                int m = k - sm.pre[e];
+                uint64_t x = sm.pixels[e];
+                int p = 0;
+#pragma unroll
+                for (int sh = 32; sh >= 1; sh >>= 1) {
+                    const int c = __popcll(x & ((1ull << sh) - 1ull));
+                    if (m >= c) {
+                        m -= c;
+                        x >>= sh;
+                        p += sh;
+                    }
+                }
+                const int lx = p & 7, ly = p >> 3;
                 const FsRecord& r = sm.rec[e];
                 const FsResp rs = fs_response(r, (double)(bp.x0 + lx - r.ax), (double)(bp.y0 + ly - r.ay));
-                if (rs.d2 <= r.k2) {
-                    const float G = __builtin_amdgcn_exp2f(neg_half_log2e * (float)rs.d2);
-                    const int p = ly * 8 + lx;
-                    sm.alpha[e][p] = fminf(o.alpha_max, r.o * G);
-                    atomicOr(&sm.mask[p], 1u << e);
-                }
+                if (rs.d2 <= r.k2) atomicOr(&sm.mask[p], 1u << e);
             }
         }
         __syncthreads();
         // (b) lane = pixel: front-to-back transmittance over its accepted
-        //     entries; blended ones keep their weight in LDS
+        //     entries (alpha recomputed from the same response: the accepted
+        //     pairs are few, and keeping alpha for every pair would cost LDS,
+        //     hence occupancy); blended entries' pairs are written in (c)
         uint32_t hit = done ? 0u : sm.mask[lane];
         uint32_t bm = 0u;
         const int c_start = cnt;
+        const double T_start = T;
+        auto alpha_of = [&](int e) {
+            const FsRecord& r = sm.rec[e];
+            const FsResp rs = fs_response(r, (double)(px - r.ax), (double)(py - r.ay));
+            const float G = __builtin_amdgcn_exp2f(neg_half_log2e * (float)rs.d2);
+            return fminf(o.alpha_max, r.o * G);
+        };
         while (hit != 0u && !done) {
             const int e = __builtin_ctz(hit);
             hit &= hit - 1u;
-            const float al = sm.alpha[e][lane];
+            const float al = alpha_of(e);
             const double Tn = T * (1.0 - (double)al);
             if (Tn < t_stop) {
                 done = true;
             } else {
-                sm.alpha[e][lane] = (float)((double)al * T);
                 bm |= 1u << e;
                 T = Tn;
                 ++cnt;
@@ -207,13 +225,19 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) used |= __shfl_xor(used, d, 64);
         {
+            // the blended entries again, in order, with the same arithmetic:
+            // w = alpha T and T *= 1 - alpha from the batch's starting T
             uint32_t mm = bm;
             int j = c_start;
+            double Tr = T_start;
             while (mm != 0u) {
                 const int e = __builtin_ctz(mm);
                 mm &= mm - 1u;
+                const float al = alpha_of(e);
+                const float w = (float)((double)al * Tr);
+                Tr = Tr * (1.0 - (double)al);
                 const uint32_t slot = nslots + (uint32_t)__popc(used & ((1u << e) - 1u));
-                mine[j] = make_uint2(slot, __float_as_uint(sm.alpha[e][lane]));
+                mine[j] = make_uint2(slot, __float_as_uint(w));
                 if (out_idx) out_idx[pix * K + j] = (int32_t)sm.recid[e];
                 ++j;
             }
