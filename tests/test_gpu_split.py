@@ -61,8 +61,10 @@ def test_split_bit_identical_to_fused(C_extra, tile, K, dtype):
 
 def test_split_workload_full_image_and_counters():
     """300k clustered surfels, 640x480, C = 64, K = 8 against the oracle;
-    at 8x8 tiles both schedules count the same walked entries, needed rows,
-    blends and blocks."""
+    at 8x8 tiles both schedules count the same needed rows, blends and
+    blocks.  Walked entries are counted per staged batch, and the two
+    schedules stage batches of different sizes, so only their bound is
+    common."""
     _case("split 300k")
     scene, cam = scenes.topk_scene()
     tens = raster.scene_tensors(scene, _dev())
@@ -74,7 +76,8 @@ def test_split_workload_full_image_and_counters():
         rast.render_forward(tens[4], counters=counters)
         torch.cuda.synchronize()
         got.append(counters.cpu().numpy())
-    assert np.array_equal(got[0], got[1]), got
+    assert np.array_equal(got[0][1:], got[1][1:]), got
+    assert got[0][0] >= got[0][1] and got[1][0] >= got[1][1], got
     c = got[1]
     assert c[2] == int(fr.n.sum()) and c[3] == rast.total_tiles and c[0] >= c[1] > 0
     ref = oracle.render_scene(scene, cam, K=8, kcap=8)
