@@ -106,9 +106,11 @@ typedef struct fs_opts {
 enum { FS_SCHED_GRID = 0, FS_SCHED_PERSISTENT = 1, FS_SCHED_SPLIT = 2 };
 
 /* Per (view, surfel), fs_preprocess leaves FS_TILE_CACHE_WORDS uint32 for
-   fs_bin: the depth key and the first FS_INLINE_TILES tiles of the footprint. */
-#define FS_INLINE_TILES 3
+   fs_bin: the depth key and, for footprints of at most FS_INLINE_TILES tiles,
+   the tiles themselves (layout under fs_preprocess). */
+#define FS_INLINE_TILES 8
 #define FS_TILE_CACHE_WORDS 4
+#define FS_TILE_CACHE_NONE 0xffffffffu
 
 /* Size of the record fs_preprocess writes per (view, surfel). */
 #define FS_RECORD_BYTES 96
@@ -141,10 +143,15 @@ size_t fs_workspace_bytes(int64_t n, int32_t num_views, int64_t total_tiles, int
  *   records        out, num_views * n * FS_RECORD_BYTES, record v*n+i
  *   tiles_touched  out, num_views * n uint32 (0 for culled surfels)
  *   tile_cache     out, num_views * n * FS_TILE_CACHE_WORDS uint32 (16-byte
- *                  aligned); for record r at [r * FS_TILE_CACHE_WORDS]: the
- *                  depth key, then the first min(count, FS_INLINE_TILES)
- *                  tiles of the footprint as view-local tx | ty << 16 (other
- *                  slots unspecified)
+ *                  aligned); words w[0..3] of record r at
+ *                  [r * FS_TILE_CACHE_WORDS]: w[0] the depth key; for a tile
+ *                  count c <= 3, w[1..c] the tiles as view-local tx | ty << 16;
+ *                  for 4 <= c <= FS_INLINE_TILES, w[1] = bx | by << 16 and byte
+ *                  k < c of w[2], w[3] (w[2] holds bytes 0-3, low byte first)
+ *                  = dx | dy << 4 for tile (bx + dx, by + dy), or w[1] =
+ *                  FS_TILE_CACHE_NONE when some tile lies more than 15 tiles
+ *                  from the base; for larger c, w[1] = FS_TILE_CACHE_NONE.
+ *                  Words not named are unspecified.
  * cams_dev is a device array of num_views cameras laid out by fs_layout_views.
  */
 fs_status fs_preprocess(const float* means, const float* scales, const float* quats, const float* opacity, int64_t n,
@@ -156,9 +163,8 @@ fs_status fs_preprocess(const float* means, const float* scales, const float* qu
  * record order, then every record writes, for each touched tile, key =
  * (global tile id << 32) | depth key and value = record index v*n+i at its
  * scanned offset.  Depth keys and tiles come from tile_cache (fs_preprocess's
- * output) when the footprint has at most FS_INLINE_TILES tiles; larger
- * footprints are re-derived from the parameters (bit-identical to
- * fs_preprocess).
+ * output) when it holds the footprint's tiles; other footprints are
+ * re-derived from the parameters (bit-identical to fs_preprocess).
  *   keys, vals       out, pair_capacity slots each
  *   num_pairs_dev    out, device int64: the pair count P (written even if it
  *                    exceeds pair_capacity; then keys beyond capacity are dropped)

@@ -6,13 +6,19 @@
 // of 1024 counts; the second has every partition add up the totals before it
 // (no workgroup ever waits on another), scan its own counts with wave-level
 // prefix sums and emit its keys.  Emission takes the depth key and the tiles
-// fs_preprocess kept for footprints of at most FS_INLINE_TILES tiles; larger
-// footprints are queued and re-derived by a second kernel with the same
-// double-precision code preprocess counted them with, so the emitted tiles
-// are exactly the counted ones.
+// fs_preprocess kept (up to FS_INLINE_TILES of them, as ids or as offsets
+// from a base tile); the other footprints are queued and re-derived by a
+// second kernel with the same double-precision code preprocess counted them
+// with, so the emitted tiles are exactly the counted ones.
 #include "fs_internal.h"
 
 namespace {
+
+// A footprint whose tiles the cache does not hold: re-derived by the
+// overflow pass.  Reads the cache only for counts it may hold in offset form.
+FS_DEV bool bin_overflows(uint32_t c, const uint4* __restrict__ tile_cache, int64_t r) {
+    return c > 3u && (c > (uint32_t)FS_INLINE_TILES || tile_cache[r].y == FS_TILE_CACHE_NONE);
+}
 
 constexpr int kThreads = 256;
 constexpr int kItems = 4;                       // counts per lane
@@ -31,10 +37,10 @@ FS_DEV uint32_t wave_inclusive_scan(uint32_t x) {
 }
 
 // Pass 1 of the scan: the total count of every partition of kPart counts and
-// its number of footprints too large for the inline tiles.
+// its number of footprints whose tiles the cache does not hold.
 __global__ void __launch_bounds__(kThreads)
-bin_sums_kernel(const uint32_t* __restrict__ counts, int64_t items, uint64_t* __restrict__ sums,
-                uint32_t* __restrict__ over_sums) {
+bin_sums_kernel(const uint32_t* __restrict__ counts, const uint4* __restrict__ tile_cache, int64_t items,
+                uint64_t* __restrict__ sums, uint32_t* __restrict__ over_sums) {
     __shared__ uint64_t s_wave[kThreads / 64];
     __shared__ uint32_t s_over[kThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -45,7 +51,7 @@ bin_sums_kernel(const uint32_t* __restrict__ counts, int64_t items, uint64_t* __
     for (int j = 0; j < kItems; ++j) {
         const uint32_t c = (base + j < items) ? counts[base + j] : 0u;
         sum += c;
-        over += c > FS_INLINE_TILES ? 1u : 0u;
+        over += bin_overflows(c, tile_cache, base + j) ? 1u : 0u;
     }
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -126,13 +132,17 @@ bin_kernel(const float* __restrict__ means, const float* __restrict__ scales, co
         *over_total = over_prefix + over_sums[part];
     }
     uint64_t off = prefix + wave_excl + (incl - sum);
-    // emission: footprints of at most FS_INLINE_TILES tiles from the ids
-    // fs_preprocess kept; larger ones go to the overflow list
+    // emission: footprints whose tiles fs_preprocess kept are emitted from
+    // the cache; the others go to the overflow list
     const int S = o.tile;
     // overflow slots in record order: partition prefix, then wave and lane
     uint32_t nover = 0;
+    bool ov[kItems];
 #pragma unroll
-    for (int j = 0; j < kItems; ++j) nover += c[j] > FS_INLINE_TILES ? 1u : 0u;
+    for (int j = 0; j < kItems; ++j) {
+        ov[j] = bin_overflows(c[j], tile_cache, base + j);
+        nover += ov[j] ? 1u : 0u;
+    }
     uint32_t over_incl = nover;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -148,7 +158,7 @@ bin_kernel(const float* __restrict__ means, const float* __restrict__ scales, co
         const int64_t r = base + j;
         const uint64_t o0 = off;
         off += c[j];
-        if (c[j] > FS_INLINE_TILES) {
+        if (ov[j]) {
             overflow[over_slot++] = make_uint2((uint32_t)r, (uint32_t)(o0 < (uint64_t)capacity ? o0 : capacity));
             continue;
         }
@@ -157,20 +167,32 @@ bin_kernel(const float* __restrict__ means, const float* __restrict__ scales, co
         const fs_camera& cam = cams[v];
         const uint32_t tiles_x = ((uint32_t)cam.width + (uint32_t)S - 1u) / (uint32_t)S;
         const uint4 cache = tile_cache[r];
-        const uint32_t id[FS_INLINE_TILES] = {cache.y, cache.z, cache.w};
         const uint64_t zk = cache.x;
-#pragma unroll
-        for (int k = 0; k < FS_INLINE_TILES; ++k) {
+        auto emit = [&](int k, uint32_t tx, uint32_t ty) {
             if ((uint32_t)k < c[j] && o0 + k < (uint64_t)capacity) {
-                const uint64_t t = (uint64_t)cam.tile_offset + (uint64_t)(id[k] >> 16) * tiles_x + (id[k] & 0xffffu);
+                const uint64_t t = (uint64_t)cam.tile_offset + (uint64_t)ty * tiles_x + tx;
                 keys[o0 + k] = (t << 32) | zk;
                 vals[o0 + k] = (uint32_t)r;
+            }
+        };
+        if (c[j] <= 3u) {
+            // the tiles themselves
+            const uint32_t id[3] = {cache.y, cache.z, cache.w};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) emit(k, id[k] & 0xffffu, id[k] >> 16);
+        } else {
+            // base tile and one byte of (dx, dy) per tile
+            const uint32_t bx = cache.y & 0xffffu, by = cache.y >> 16;
+#pragma unroll
+            for (int k = 0; k < FS_INLINE_TILES; ++k) {
+                const uint32_t b = ((k < 4 ? cache.z : cache.w) >> (8 * (k & 3))) & 0xffu;
+                emit(k, bx + (b & 15u), by + (b >> 4));
             }
         }
     }
 }
 
-// Footprints with more tiles than the inline ids hold: one lane per record,
+// Footprints whose tiles the cache does not hold: one lane per record,
 // re-derived from the parameters with the code fs_preprocess counted them with.
 __global__ void __launch_bounds__(kThreads)
 bin_overflow_kernel(const float* __restrict__ means, const float* __restrict__ scales,
@@ -226,8 +248,8 @@ hipError_t fs_launch_bin(const float* means, const float* scales, const float* q
         hipLaunchKernelGGL(zero_count_kernel, dim3(1), dim3(1), 0, s, num_pairs);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(bin_sums_kernel, dim3((unsigned)parts), dim3(kThreads), 0, s, tiles_touched, items,
-                       ws.scan_status, ws.bin_over_sums);
+    hipLaunchKernelGGL(bin_sums_kernel, dim3((unsigned)parts), dim3(kThreads), 0, s, tiles_touched,
+                       reinterpret_cast<const uint4*>(tile_cache), items, ws.scan_status, ws.bin_over_sums);
     hipLaunchKernelGGL(bin_kernel, dim3((unsigned)parts), dim3(kThreads), 0, s, means, scales, quats, opacity, n, cams, o,
                        tiles_touched, reinterpret_cast<const uint4*>(tile_cache), items, ws.bin_overflow, keys, vals,
                        capacity, num_pairs, ws.scan_status, ws.bin_over_sums, ws.scan_ticket + 1, parts);

@@ -535,10 +535,10 @@ FS_DEV int64_t xcd_remap(int64_t g, int64_t G) {
 struct FsWorkspace {
     // bin (scan + emit)
     uint64_t* scan_status;   // partition totals
-    uint32_t* bin_over_sums; // per partition: footprints with more than FS_INLINE_TILES tiles
+    uint32_t* bin_over_sums; // per partition: footprints whose tiles the tile cache does not hold
     uint32_t* scan_ticket;   // [1]: overflow count
     int64_t scan_parts;
-    uint2* bin_overflow;     // (record, first offset) of footprints with more than FS_INLINE_TILES tiles
+    uint2* bin_overflow;     // (record, first offset) of those footprints
     // sort
     uint32_t* tile_cnt;      // pairs per tile
     uint32_t* tile_fill;     // scatter cursor per tile

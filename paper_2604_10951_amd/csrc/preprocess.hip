@@ -6,13 +6,15 @@
 // tile count is the exact per-pixel footprint count.
 #include "fs_internal.h"
 
-static_assert(FS_INLINE_TILES == 3 && FS_TILE_CACHE_WORDS == 4, "the cache is one uint4 per record");
+static_assert(FS_INLINE_TILES == 8 && FS_TILE_CACHE_WORDS == 4, "the cache is one uint4 per record");
 
 namespace {
 
 constexpr int kThreads = 256;
 
-__global__ void __launch_bounds__(kThreads)
+// at least four waves per SIMD (128 VGPRs): the double-precision sweep is
+// latency-bound and needs the occupancy
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 preprocess_kernel(const float* __restrict__ means, const float* __restrict__ scales, const float* __restrict__ quats,
                   const float* __restrict__ opacity, int64_t n, const fs_camera* __restrict__ cams, fs_opts o,
                   FsRecord* __restrict__ records, uint32_t* __restrict__ tiles_touched, uint4* __restrict__ tile_cache) {
@@ -33,11 +35,24 @@ preprocess_kernel(const float* __restrict__ means, const float* __restrict__ sca
     rec.y0 = 1;
     rec.y1 = 0;
     uint32_t count = 0;
-    uint32_t ids[FS_INLINE_TILES] = {0u, 0u, 0u};   // first tiles of the footprint, tx | ty << 16
+    // the footprint's tiles for fs_bin: the first three as tx | ty << 16, and
+    // the first eight as 4-bit offsets from the base tile (bx, by) of its
+    // candidate range, while every offset fits
+    uint32_t ids[3] = {0u, 0u, 0u};
+    uint32_t off[2] = {0u, 0u};
+    bool fits = true;
+    int bx = 0, by = 0;
     auto note = [&](int tx, int ty) {
 #pragma unroll
-        for (int k = 0; k < FS_INLINE_TILES; ++k)
+        for (int k = 0; k < 3; ++k)
             if (count == (uint32_t)k) ids[k] = (uint32_t)tx | ((uint32_t)ty << 16);
+        const int dx = tx - bx, dy = ty - by;
+        fits = fits && dx >= 0 && dx <= 15 && dy >= 0 && dy <= 15;
+        const uint32_t byte = (uint32_t)(dx & 15) | ((uint32_t)(dy & 15) << 4);
+        if (count < 4u)
+            off[0] |= byte << (8u * count);
+        else if (count < 8u)
+            off[1] |= byte << (8u * (count - 4u));
         ++count;
     };
     FsGeo g;
@@ -50,6 +65,8 @@ preprocess_kernel(const float* __restrict__ means, const float* __restrict__ sca
                 int tx0, tx1, ty0, ty1;
                 if (fs_bbox_tiles(fp, cam.width, cam.height, S, tx0, tx1, ty0, ty1)) {
                     const uint32_t nt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+                    bx = tx0;
+                    by = ty0;
                     if (nt <= FS_INLINE_TILES) {
                         for (int ty = ty0; ty <= ty1; ++ty)
                             for (int tx = tx0; tx <= tx1; ++tx) note(tx, ty);
@@ -58,6 +75,8 @@ preprocess_kernel(const float* __restrict__ means, const float* __restrict__ sca
                     }
                 }
             } else {
+                bx = fp.px0 / S;
+                by = fp.py0 / S;
                 fs_sweep_tiles(fp, S, note);
             }
         }
@@ -89,7 +108,12 @@ preprocess_kernel(const float* __restrict__ means, const float* __restrict__ sca
     }
     records[r] = rec;
     tiles_touched[r] = count;
-    tile_cache[r] = make_uint4(g.zkey, ids[0], ids[1], ids[2]);
+    if (count <= 3u)
+        tile_cache[r] = make_uint4(g.zkey, ids[0], ids[1], ids[2]);
+    else if (count <= (uint32_t)FS_INLINE_TILES && fits)
+        tile_cache[r] = make_uint4(g.zkey, (uint32_t)bx | ((uint32_t)by << 16), off[0], off[1]);
+    else
+        tile_cache[r] = make_uint4(g.zkey, FS_TILE_CACHE_NONE, 0u, 0u);
 }
 
 }  // namespace

@@ -219,6 +219,21 @@ def random_lookat_views(n_views: int, *, seed: int = 0, centre=(0.0, 0.0, 22.5),
 # The workloads used by tests and the benchmark.
 # ---------------------------------------------------------------------------
 
+def needle_scene(n: int = 400, *, seed: int = 5) -> tuple[Scene, Camera]:
+    """Long, very thin surfels at shallow slopes, 512x128: the footprint
+    crosses pixel centres only every few tens of pixels, so many surfels touch
+    a handful of tiles spread over more than 16 tile columns (the sparse
+    footprints whose tiles the compact tile cache cannot hold)."""
+    rng = np.random.default_rng(seed)
+    th = rng.uniform(0.015, 0.04, n) * rng.choice([-1.0, 1.0], n)
+    quats = np.stack([np.cos(th / 2), 0 * th, 0 * th, np.sin(th / 2)], 1).astype(np.float32)
+    means = np.stack([rng.uniform(-0.3, 0.3, n), rng.uniform(-0.3, 0.3, n), np.full(n, 4.0)], 1).astype(np.float32)
+    scales = np.stack([rng.uniform(0.3, 0.6, n), np.full(n, 2e-5)], 1).astype(np.float32)
+    opacity = np.full(n, 0.9, np.float32)
+    feats = rng.standard_normal((n, 4)).astype(np.float32)
+    return Scene(means, scales, quats, opacity, feats), centred_camera(512, 128)
+
+
 def parity_small(seed: int = 0) -> tuple[Scene, Camera]:
     """2,000 surfels, 128x128, RGB + 16 feature channels (C = 19)."""
     return uniform_scene(2000, seed=seed), centred_camera(128, 128)

@@ -292,3 +292,17 @@ def test_sort_long_tile_runs():
     runs = (fr.ranges[:, 1] - fr.ranges[:, 0]).cpu().numpy()
     assert runs.max() > 8192 and ((runs > 1024) & (runs <= 8192)).any() or runs.max() > 8192, runs
     assert check_pairs(fr, sc, cam, 32) > 8192
+
+
+def test_sparse_footprints_pairs_and_image():
+    """Needle surfels: footprints of 4-8 tiles more than 15 tiles apart (kept
+    out of the compact tile cache and re-derived), of more than 8 tiles and of
+    at most 3; sorted pairs bit-exact and the full blend within tolerance."""
+    _print_case("sparse needle footprints")
+    scene, cam = scenes.needle_scene()
+    for tile in (8, 16):
+        rast, fr = _render(scene, cam, tile=tile)
+        assert check_pairs(fr, scene, cam, tile) > 1000
+    ref = oracle.render_scene(scene, cam, kcap=256)
+    rast, fr = _render(scene, cam, tile=8)
+    check_image(fr, ref, rast, 0, scene.channels, 0, "needles")

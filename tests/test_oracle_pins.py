@@ -381,3 +381,24 @@ def test_gradient_absolute_term_sums_bound_the_gradient():
     # of the same blend with |g| as upstream gradient
     ga = oracle.render_grad(sc.means, sc.scales, sc.quats, sc.opacity, sc.feats, cam, np.abs(g), K=3)
     np.testing.assert_allclose(gr.abs.feats, ga.feats, rtol=1e-12, atol=1e-15)
+
+
+def test_needle_scene_has_sparse_footprints():
+    """The needle workload of the GPU pair tests really holds footprints of
+    4-8 tiles spread over more than 15 tiles (they cannot be stored as 4-bit
+    offsets), footprints of more than 8 tiles and footprints of 1-3 tiles."""
+    from paper_2604_10951_amd import scenes
+    scene, cam = scenes.needle_scene()
+    proj = oracle.project_scene(scene, cam)
+    counts, flags, keys, vals = oracle.tile_sets(proj, cam.width, cam.height, 8, pairs=True)
+    assert (flags != 0).sum() == 0
+    tiles_x = (cam.width + 7) // 8
+    t = (keys >> np.uint64(32)).astype(np.int64)
+    tx, ty = t % tiles_x, t // tiles_x
+    span = np.zeros(scene.n, np.int64)
+    for r in np.unique(vals):
+        m = vals == r
+        span[r] = max(tx[m].max() - tx[m].min(), ty[m].max() - ty[m].min())
+    sparse = (counts >= 4) & (counts <= 8) & (span > 15)
+    assert sparse.sum() >= 50
+    assert (counts > 8).sum() >= 3 and ((counts >= 1) & (counts <= 3)).sum() >= 3
