@@ -418,13 +418,14 @@ topk_grad_kernel(const FsRecord* __restrict__ records, const uint2* __restrict__
     __shared__ int s_sfill[kPairs];          // per row slot: pairs, then the fill cursor
     __shared__ uint16_t s_list[kPairs];      // pair indices p * K + j grouped by row slot
     __shared__ int s_cnt[64];
+    __shared__ int s_off[64];                // first pair of each pixel's compact list
     __shared__ int s_wave[kGradThreads / 64];
     __shared__ float s_grec[kGradSlots][10];   // dL/dL and dL/do of the first kGradSlots row slots
     const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t block = xcd_remap(blockIdx.x, nblocks);
     const BlockPos bp = locate_block(block, S, 8, cams, num_views);
     if (!bp.valid) return;           // uniform
-    const uint32_t R = nrows[block];
+    const uint32_t R = nrows[block] & 0xffffu;   // rows (the high half counts the listed pairs)
     if (R == 0) return;              // no pixel of the block blended anything
     const fs_camera& cam = cams[bp.view];
     const int nv = C / VE;           // channel vectors per row (C % VE == 0)
@@ -432,13 +433,26 @@ topk_grad_kernel(const FsRecord* __restrict__ records, const uint2* __restrict__
     const bool has_vec = q < nv;
     const uint32_t* __restrict__ rowlist = rows + block * 64 * (int64_t)K;
     const int npairs = 64 * K;
-    for (int t = tid; t < npairs; t += kGradThreads) {
-        s_pairs[t] = pairs[block * 64 * (int64_t)K + t];
-        s_sfill[t] = 0;
-    }
+    for (int t = tid; t < npairs; t += kGradThreads) s_sfill[t] = 0;
     if (tid < 64) {
+        // counts, and the offsets of the pixels' lists in the block's compact
+        // list area (the selection writes them back to back)
         const int px = bp.x0 + (tid & 7), py = bp.y0 + (tid >> 3);
-        s_cnt[tid] = (px < cam.width && py < cam.height) ? counts[cam.pixel_offset + (int64_t)py * cam.width + px] : 0;
+        const int c = (px < cam.width && py < cam.height) ? counts[cam.pixel_offset + (int64_t)py * cam.width + px] : 0;
+        int incl = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(incl, d, 64);
+            if (tid >= d) incl += y;
+        }
+        s_cnt[tid] = c;
+        s_off[tid] = incl - c;
+    }
+    __syncthreads();
+    // pair j of pixel p at LDS p * K + j
+    for (int t = tid; t < npairs; t += kGradThreads) {
+        const int p = t / K, j = t - p * K;
+        if (j < s_cnt[p]) s_pairs[t] = pairs[block * 64 * (int64_t)K + s_off[p] + j];
     }
     __syncthreads();
     // 1a. pairs grouped by row slot (counting sort in LDS)

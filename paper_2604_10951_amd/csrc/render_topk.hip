@@ -30,6 +30,9 @@ constexpr int kGatherUnroll = 8;  // (surfel, weight) pairs whose row loads are 
 constexpr int kStagedK = 16;      // largest K of the staged gather (its lists live in LDS)
 
 
+// KC > 0: every pixel's list (at most KC pairs) is kept in LDS during the
+// walk and written compactly at the end; KC = 0: lists written in place.
+template <int KC>
 struct SelShared {
     FsRecord rec[kSelBatch];
     uint32_t recid[kSelBatch];
@@ -37,8 +40,14 @@ struct SelShared {
     int pre[kSelBatch];            // exclusive prefix of the entries' pair counts
     uint64_t pixels[kSelBatch];    // per entry: pixels of the block inside its box that are still walking
     uint32_t mask[64];             // per pixel: entries of the batch it accepts
+    uint2 list[64 * (KC > 0 ? KC : 1)];   // per pixel: (batch entry, then row slot; weight)
 };
 
+// List layout in the workspace, per 8x8 block b (region b * 64 * K of the
+// pair array): with KC > 0 the pairs of pixel p start at the sum of the
+// counts of pixels 0 .. p - 1 (compact), and nrows[b] = rows | pairs << 16;
+// with KC = 0 they start at p * K and nrows[b] = rows.
+template <int KC>
 __global__ void __launch_bounds__(64)
 topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restrict__ vals,
                    const uint32_t* __restrict__ ranges, uint32_t n, int64_t num_records,
@@ -49,7 +58,7 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
     constexpr int BG = kSelBatch;
     constexpr int kQ = FS_RECORD_BYTES / 16;          // float4 per record
     constexpr int kRecSlots = (BG * kQ + 63) / 64;    // record float4 per lane
-    __shared__ SelShared sm;
+    __shared__ SelShared<KC> sm;
     const int lane = threadIdx.x;
     const int64_t block = xcd_remap(blockIdx.x, nblocks);
     const BlockPos bp = locate_block(block, S, 8, cams, num_views);
@@ -193,7 +202,8 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
         // (b) lane = pixel: front-to-back transmittance over its accepted
         //     entries (alpha recomputed from the same response: the accepted
         //     pairs are few, and keeping alpha for every pair would cost LDS,
-        //     hence occupancy); blended entries' pairs are written in (c)
+        //     hence occupancy); with KC > 0 every blended entry's weight
+        //     w = alpha T goes to the pixel's LDS list here
         uint32_t hit = done ? 0u : sm.mask[lane];
         uint32_t bm = 0u;
         const int c_start = cnt;
@@ -213,6 +223,10 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
                 done = true;
             } else {
                 bm |= 1u << e;
+                if constexpr (KC > 0) {
+                    sm.list[lane * KC + cnt] = make_uint2((uint32_t)e, __float_as_uint((float)((double)al * T)));
+                    if (out_idx) out_idx[pix * K + cnt] = (int32_t)sm.recid[e];
+                }
                 T = Tn;
                 ++cnt;
                 last = (int)(b0 + e);
@@ -224,7 +238,12 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
         uint32_t used = bm;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) used |= __shfl_xor(used, d, 64);
-        {
+        if constexpr (KC > 0) {
+            for (int j = c_start; j < cnt; ++j) {
+                const uint32_t e = sm.list[lane * KC + j].x;
+                sm.list[lane * KC + j].x = nslots + (uint32_t)__popc(used & ((1u << e) - 1u));
+            }
+        } else {
             // the blended entries again, in order, with the same arithmetic:
             // w = alpha T and T *= 1 - alpha from the batch's starting T
             uint32_t mm = bm;
@@ -259,7 +278,21 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
             atomicAdd((unsigned long long*)&counters[3], 1ull);
         }
     }
-    if (lane == 0) nrows[block] = nslots;
+    if constexpr (KC > 0) {
+        // compact lists: pixel p's pairs after those of pixels 0 .. p - 1
+        int incl = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += y;
+        }
+        const int total = __shfl(incl, 63, 64);
+        uint2* __restrict__ dst = pairs + block * 64 * (int64_t)K + (incl - cnt);
+        for (int j = 0; j < cnt; ++j) dst[j] = sm.list[lane * KC + j];
+        if (lane == 0) nrows[block] = nslots | ((uint32_t)total << 16);
+    } else {
+        if (lane == 0) nrows[block] = nslots;
+    }
     if (inside) {
         if (out_T) out_T[pix] = (float)T;
         out_n[pix] = cnt;
@@ -332,18 +365,37 @@ topk_gather_general_kernel(const uint2* __restrict__ pairs, const int32_t* __res
     using V = Vec<FT, VE>;
     constexpr int kPix = kGatherThreads / TPP;   // pixels per workgroup
     constexpr int kGroups = 64 / kPix;           // workgroups per block
+    __shared__ int s_off[64];
     const int64_t g = xcd_remap(blockIdx.x, ngroups);
     const int64_t block = g / kGroups;
     const BlockPos bp = locate_block(block, S, 8, cams, num_views);
-    if (!bp.valid) return;
+    if (!bp.valid) return;   // uniform over the workgroup
     const fs_camera& cam = cams[bp.view];
+    const bool compact = K <= kStagedK;   // the selection's list layout
+    if (compact) {
+        // offsets of the pixels' lists: prefix of the block's counts
+        const int t = (int)threadIdx.x;
+        if (t < 64) {
+            const int qx = bp.x0 + (t & 7), qy = bp.y0 + (t >> 3);
+            const int c = (qx < cam.width && qy < cam.height) ? counts[cam.pixel_offset + (int64_t)qy * cam.width + qx]
+                                                              : 0;
+            int incl = c;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int y = __shfl_up(incl, d, 64);
+                if (t >= d) incl += y;
+            }
+            s_off[t] = incl - c;
+        }
+        __syncthreads();
+    }
     const int p = (int)(g % kGroups) * kPix + (int)threadIdx.x / TPP;   // pixel of the block
     const int q0 = (int)threadIdx.x % TPP;
     const int px = bp.x0 + (p & 7), py = bp.y0 + (p >> 3);
     if (px >= cam.width || py >= cam.height) return;
     const int64_t pix = cam.pixel_offset + (int64_t)py * cam.width + px;
     const int cnt = counts[pix];
-    const uint2* __restrict__ mine = pairs + (block * 64 + p) * (int64_t)K;
+    const uint2* __restrict__ mine = pairs + block * 64 * (int64_t)K + (compact ? s_off[p] : p * K);
     const uint32_t* __restrict__ rowlist = rows + block * 64 * (int64_t)K;
     const int nv = (C + VE - 1) / VE;
     float* __restrict__ dst = out_feat + pix * C;
@@ -395,8 +447,9 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
     constexpr int kPix = kGatherThreads / TPP;   // pixels per pass
     constexpr int kPasses = 64 / kPix;           // pixels per thread
     __shared__ __align__(16) uint4 s_rows[W * TPP];   // W rows of at most TPP vectors
-    __shared__ uint2 s_pairs[64 * kStagedK];
+    __shared__ uint2 s_pairs[64 * kStagedK];   // the block's compact lists
     __shared__ int s_cnt[64];
+    __shared__ int s_off[64];                  // first pair of each pixel's list
     __shared__ uint32_t s_rowid[W];
     const int tid = (int)threadIdx.x;
     const int64_t block = xcd_remap(blockIdx.x, nblocks);
@@ -406,12 +459,13 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
     const int nv = C / VE;                       // vectors per row (C % VE == 0)
     const int q = tid % TPP, sub = tid / TPP;
     const bool has_vec = q < nv;
-    const uint32_t R = nrows[block];
+    const uint32_t nr = nrows[block];
+    const uint32_t R = nr & 0xffffu, NP = nr >> 16;   // rows and listed pairs of the block
     const uint32_t* __restrict__ rowlist = rows + block * 64 * (int64_t)K;
     // lists, counts and the first window's row ids: one round trip (a block
     // no pixel of which blends anything has R = 0 and only writes zeros)
     if (R > 0)
-        for (int t = tid; t < 64 * K; t += kGatherThreads) s_pairs[t] = pairs[block * 64 * (int64_t)K + t];
+        for (int t = tid; t < (int)NP; t += kGatherThreads) s_pairs[t] = pairs[block * 64 * (int64_t)K + t];
     if (tid < 64 && R > 0) {
         const int px = bp.x0 + (tid & 7), py = bp.y0 + (tid >> 3);
         s_cnt[tid] = (px < cam.width && py < cam.height) ? counts[cam.pixel_offset + (int64_t)py * cam.width + px] : 0;
@@ -426,6 +480,16 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
         for (int i = 0; i < VE; ++i) acc[k][i] = 0.f;
     }
     __syncthreads();
+    if (tid < 64) {
+        const int c = s_cnt[tid];
+        int incl = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(incl, d, 64);
+            if (tid >= d) incl += y;
+        }
+        s_off[tid] = incl - c;   // visible after the staging barrier below
+    }
     for (uint32_t s0 = 0; s0 < R; s0 += W) {
         const int nw = (int)(R - s0 < (uint32_t)W ? R - s0 : (uint32_t)W);
         // stage rows [s0, s0 + nw): vector v of the window is row v / nv,
@@ -449,7 +513,7 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
             const int c = s_cnt[p];
             int j = cur[k];
             while (j < c) {
-                const uint2 pr = s_pairs[p * K + j];
+                const uint2 pr = s_pairs[s_off[p] + j];
                 if (pr.x >= s0 + (uint32_t)nw) break;
                 if (has_vec) {
                     const typename V::raw f = *reinterpret_cast<const typename V::raw*>(
@@ -528,9 +592,11 @@ hipError_t fs_launch_topk_select(const FsRecord* records, const uint32_t* vals, 
     if (ws.topk_pairs == nullptr || ws.topk_rows == nullptr || ws.topk_nrows == nullptr ||
         ws.topk_pair_slots < nblocks * 64 * (int64_t)o.topk || nblocks >= (int64_t(1) << 31))
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(topk_select_kernel, dim3((unsigned)nblocks), dim3(64), 0, s, records, vals, ranges,
-                       (uint32_t)n, n * num_views, cams, num_views, o.tile, o, nblocks,
-                       ws.topk_pairs, ws.topk_rows, ws.topk_nrows, out_T, out_n, out_last, out_idx, counters);
+    auto kern = o.topk <= 8 ? topk_select_kernel<8> : (o.topk <= kStagedK ? topk_select_kernel<kStagedK>
+                                                                          : topk_select_kernel<0>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(64), 0, s, records, vals, ranges, (uint32_t)n,
+                       n * num_views, cams, num_views, o.tile, o, nblocks, ws.topk_pairs, ws.topk_rows,
+                       ws.topk_nrows, out_T, out_n, out_last, out_idx, counters);
     return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@
 //      cursor (any order inside the tile);
 //   2. a sort of every tile's run by (depth key, record), as 64-bit composite
 //      keys: runs of up to kWaveCap entries by one wave each (bitonic network
-//      in the wave's LDS slice), up to kLargeCap by a workgroup (bitonic in
+//      in the wave's registers), up to kLargeCap by a workgroup (bitonic in
 //      64 KB of LDS), longer runs by a stable one-workgroup LSD radix sort
 //      through global memory.
 // Every launch is sized from the capacity, not from the device-side pair
@@ -22,7 +22,7 @@
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kWaveCap = 512;     // entries per run sorted by one wave (4 KB of LDS per wave)
+constexpr int kWaveCap = 512;     // entries per run sorted by one wave (8 per lane, in registers)
 constexpr int kLargeCap = 8192;   // entries per run sorted in LDS by a workgroup (64 KB)
 constexpr int kLdsTiles = 16384;  // tile counts kept in LDS by the count and scatter kernels
 constexpr int kChunk = 8192;      // pairs per workgroup in the count and scatter kernels
@@ -259,15 +259,71 @@ FS_DEV void sort_run_lds(uint64_t* s, const uint2* __restrict__ in, uint64_t til
     }
 }
 
-// One wave per tile: runs of up to kWaveCap entries are sorted by a bitonic
-// network in the wave's own LDS slice (a wave's LDS accesses complete in
-// order, so stages need no workgroup barrier); longer runs are appended to
-// the list the long-run kernel works through.
+// Bitonic sort of one run of 1 <= n <= 64 E entries by one wave, in
+// registers: element i = lane * E + e of the padded run (padding = ~0) is
+// x[e] of its lane.  Compare-exchange partners i ^ j with j < E sit in the
+// same lane; with j >= E they are the same register of lane ^ (j / E),
+// fetched by a shuffle.  The network is the textbook one (stage k, distance
+// j, ascending where i & k == 0), so the result is the sorted run.
+template <int LOGE>
+FS_DEV void sort_run_wave(const uint2* __restrict__ in, uint64_t tile, uint32_t start, int n,
+                          uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    constexpr int E = 1 << LOGE;
+    constexpr int LOGN = 6 + LOGE;
+    const int lane = (int)threadIdx.x & 63;
+    uint64_t x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = lane * E + e;
+        x[e] = i < n ? composite(in[start + i]) : ~0ull;
+    }
+#pragma unroll
+    for (int lk = 1; lk <= LOGN; ++lk) {
+        const int k = 1 << lk;
+#pragma unroll
+        for (int lj = lk - 1; lj >= 0; --lj) {
+            const int j = 1 << lj;
+            if (lj >= LOGE) {
+                const int lm = j >> LOGE;   // lane distance
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int i = lane * E + e;
+                    const uint64_t y = __shfl_xor(x[e], lm, 64);
+                    const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
+                    const bool lt = y < x[e];
+                    x[e] = (keep_min == lt) ? y : x[e];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    if ((e & j) != 0) continue;
+                    const int i = lane * E + e;
+                    const uint64_t a = x[e], b = x[e | j];
+                    const bool swap = (b < a) == ((i & k) == 0);
+                    x[e] = swap ? b : a;
+                    x[e | j] = swap ? a : b;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = lane * E + e;
+        if (i < n) {
+            keys[start + i] = (tile << 32) | (x[e] >> 32);
+            vals[start + i] = (uint32_t)x[e];
+        }
+    }
+}
+
+// One wave per tile: runs of up to kWaveCap entries are sorted in the wave's
+// registers (1, 2, 4 or 8 entries per lane by run length); longer runs are
+// appended to the list the long-run kernel works through.
 __global__ void __launch_bounds__(kThreads)
 sort_short_runs_kernel(const uint2* __restrict__ in, const uint32_t* __restrict__ ranges, int64_t tiles,
                        uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ long_list,
                        uint32_t* __restrict__ long_count) {
-    __shared__ uint64_t s_all[kThreads / 64][kWaveCap];
+    static_assert(kWaveCap == 512, "runs up to 8 entries per lane");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t t = (int64_t)blockIdx.x * (kThreads / 64) + wave;
     if (t >= tiles) return;   // uniform per wave
@@ -278,34 +334,14 @@ sort_short_runs_kernel(const uint2* __restrict__ in, const uint32_t* __restrict_
         if (lane == 0) long_list[atomicAdd(long_count, 1u)] = (uint32_t)t;
         return;
     }
-    uint64_t* s = s_all[wave];
-    const int n2 = next_pow2(n < 2 ? 2 : n);
-    for (int i = lane; i < n2; i += 64) s[i] = i < n ? composite(in[start + i]) : ~0ull;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int k = 2; k <= n2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = lane; i < (n2 >> 1); i += 64) {
-                const int a = ((i & ~(j - 1)) << 1) | (i & (j - 1));
-                const int b = a + j;
-                const bool up = (a & k) == 0;
-                const uint64_t x = s[a], y = s[b];
-                if ((x > y) == up) {
-                    s[a] = y;
-                    s[b] = x;
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        }
-    }
-    for (int i = lane; i < n; i += 64) {
-        const uint64_t c = s[i];
-        keys[start + i] = ((uint64_t)t << 32) | (c >> 32);
-        vals[start + i] = (uint32_t)c;
-    }
+    if (n <= 64)
+        sort_run_wave<0>(in, (uint64_t)t, start, n, keys, vals);
+    else if (n <= 128)
+        sort_run_wave<1>(in, (uint64_t)t, start, n, keys, vals);
+    else if (n <= 256)
+        sort_run_wave<2>(in, (uint64_t)t, start, n, keys, vals);
+    else
+        sort_run_wave<3>(in, (uint64_t)t, start, n, keys, vals);
 }
 
 // Stable LSD radix sort of one run through global memory, 8-bit digits of the
