@@ -532,6 +532,12 @@ FS_DEV int64_t xcd_remap(int64_t g, int64_t G) {
 // ---------------------------------------------------------------------------
 // Host-side launch helpers implemented in the .hip files.
 // ---------------------------------------------------------------------------
+// Top-K lists in the workspace: for K <= FS_TOPK_COMPACT_K the selection
+// writes every 8x8 block's per-pixel (row slot, weight) lists back to back
+// (pixel p after pixels 0 .. p - 1) and the block's row count as
+// rows | pairs << 16; for larger K pixel p's list starts at p * K.
+constexpr int FS_TOPK_COMPACT_K = 16;
+
 struct FsWorkspace {
     // bin (scan + emit)
     uint64_t* scan_status;   // partition totals

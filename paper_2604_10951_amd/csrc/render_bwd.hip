@@ -371,6 +371,7 @@ preprocess_bwd_kernel(const float* __restrict__ means, const float* __restrict__
 // ---------------------------------------------------------------------------
 constexpr int kGradThreads = 256;
 constexpr int kGradMaxK = 16;
+static_assert(kGradMaxK <= FS_TOPK_COMPACT_K, "the gradient pass reads compact lists");
 constexpr int kGradSlots = 256;   // row slots whose geometry gradients are summed in LDS
 
 template <typename FT>

@@ -28,6 +28,8 @@ constexpr int kSelBatch = 32;   // list entries staged per step in the selection
 constexpr int kGatherThreads = 256;
 constexpr int kGatherUnroll = 8;  // (surfel, weight) pairs whose row loads are in flight together
 constexpr int kStagedK = 16;      // largest K of the staged gather (its lists live in LDS)
+constexpr int kCompactK = FS_TOPK_COMPACT_K;   // K up to which the selection writes compact lists
+static_assert(kStagedK <= kCompactK, "the staged gather reads compact lists");
 
 
 // KC > 0: every pixel's list (at most KC pairs) is kept in LDS during the
@@ -371,7 +373,7 @@ topk_gather_general_kernel(const uint2* __restrict__ pairs, const int32_t* __res
     const BlockPos bp = locate_block(block, S, 8, cams, num_views);
     if (!bp.valid) return;   // uniform over the workgroup
     const fs_camera& cam = cams[bp.view];
-    const bool compact = K <= kStagedK;   // the selection's list layout
+    const bool compact = K <= kCompactK;   // the selection's list layout
     if (compact) {
         // offsets of the pixels' lists: prefix of the block's counts
         const int t = (int)threadIdx.x;
@@ -436,7 +438,7 @@ topk_gather_general_kernel(const uint2* __restrict__ pairs, const int32_t* __res
 // in flight together), and every pixel adds the rows of its list that fall
 // in the window, front to back.  TPP threads per pixel, each owning one
 // 16-byte channel vector of kPasses pixels of the block.
-template <typename FT, int TPP, int W>
+template <typename FT, int TPP, int W, int KC>
 __global__ void __launch_bounds__(kGatherThreads)
 topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restrict__ counts,
                        const uint32_t* __restrict__ rows, const uint32_t* __restrict__ nrows,
@@ -447,7 +449,7 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
     constexpr int kPix = kGatherThreads / TPP;   // pixels per pass
     constexpr int kPasses = 64 / kPix;           // pixels per thread
     __shared__ __align__(16) uint4 s_rows[W * TPP];   // W rows of at most TPP vectors
-    __shared__ uint2 s_pairs[64 * kStagedK];   // the block's compact lists
+    __shared__ uint2 s_pairs[64 * KC];   // the block's compact lists (K <= KC)
     __shared__ int s_cnt[64];
     __shared__ int s_off[64];                  // first pair of each pixel's list
     __shared__ uint32_t s_rowid[W];
@@ -551,9 +553,14 @@ hipError_t launch_gather(const uint2* pairs, const int32_t* counts, const uint32
     while (tpp < nv && tpp < 64) tpp <<= 1;
     if (VE > 1 && nv <= 64 && K <= kStagedK) {
         if (nblocks >= (int64_t(1) << 32)) return hipErrorInvalidValue;
-#define FS_GATHER_LDS(TPP, W)                                                                                 \
-    hipLaunchKernelGGL((topk_gather_lds_kernel<FT, TPP, W>), dim3((unsigned)nblocks), dim3(kGatherThreads), 0, \
-                       s, pairs, counts, rows, nrows, f, C, K, cams, num_views, S, nblocks, out_feat)
+#define FS_GATHER_LDS(TPP, W)                                                                                     \
+    if (K <= 8)                                                                                                    \
+        hipLaunchKernelGGL((topk_gather_lds_kernel<FT, TPP, W, 8>), dim3((unsigned)nblocks), dim3(kGatherThreads), \
+                           0, s, pairs, counts, rows, nrows, f, C, K, cams, num_views, S, nblocks, out_feat);      \
+    else                                                                                                           \
+        hipLaunchKernelGGL((topk_gather_lds_kernel<FT, TPP, W, kStagedK>), dim3((unsigned)nblocks),                \
+                           dim3(kGatherThreads), 0, s, pairs, counts, rows, nrows, f, C, K, cams, num_views, S,   \
+                           nblocks, out_feat)
         // windows of about 24 KB of rows
         switch (tpp) {
             case 4: FS_GATHER_LDS(4, 64); break;
@@ -592,8 +599,8 @@ hipError_t fs_launch_topk_select(const FsRecord* records, const uint32_t* vals, 
     if (ws.topk_pairs == nullptr || ws.topk_rows == nullptr || ws.topk_nrows == nullptr ||
         ws.topk_pair_slots < nblocks * 64 * (int64_t)o.topk || nblocks >= (int64_t(1) << 31))
         return hipErrorInvalidValue;
-    auto kern = o.topk <= 8 ? topk_select_kernel<8> : (o.topk <= kStagedK ? topk_select_kernel<kStagedK>
-                                                                          : topk_select_kernel<0>);
+    auto kern = o.topk <= 8 ? topk_select_kernel<8> : (o.topk <= kCompactK ? topk_select_kernel<kCompactK>
+                                                                           : topk_select_kernel<0>);
     hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(64), 0, s, records, vals, ranges, (uint32_t)n,
                        n * num_views, cams, num_views, o.tile, o, nblocks, ws.topk_pairs, ws.topk_rows,
                        ws.topk_nrows, out_T, out_n, out_last, out_idx, counters);
