@@ -140,7 +140,9 @@ size_t fs_workspace_bytes(int64_t n, int32_t num_views, int64_t total_tiles, int
  * the depth key (float32 bits of the centre's camera depth), culling, the
  * cutoff k^2 = 2 ln(o / alpha_min), the screen conic of u^2+v^2 = k^2 and its
  * tile count (exact per-pixel footprint for FS_TILES_PRECISE).
- *   records        out, num_views * n * FS_RECORD_BYTES, record v*n+i
+ *   records        out, num_views * n * FS_RECORD_BYTES, record v*n+i; written
+ *                  only for surfels with a nonzero tile count (the only ones a
+ *                  key list refers to), others left untouched
  *   tiles_touched  out, num_views * n uint32 (0 for culled surfels)
  *   tile_cache     out, num_views * n * FS_TILE_CACHE_WORDS uint32 (16-byte
  *                  aligned); words w[0..3] of record r at
@@ -151,7 +153,8 @@ size_t fs_workspace_bytes(int64_t n, int32_t num_views, int64_t total_tiles, int
  *                  = dx | dy << 4 for tile (bx + dx, by + dy), or w[1] =
  *                  FS_TILE_CACHE_NONE when some tile lies more than 15 tiles
  *                  from the base; for larger c, w[1] = FS_TILE_CACHE_NONE.
- *                  Words not named are unspecified.
+ *                  Words not named are unspecified; nothing is written for
+ *                  c = 0.
  * cams_dev is a device array of num_views cameras laid out by fs_layout_views.
  */
 fs_status fs_preprocess(const float* means, const float* scales, const float* quats, const float* opacity, int64_t n,

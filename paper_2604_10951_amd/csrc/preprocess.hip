@@ -106,8 +106,9 @@ preprocess_kernel(const float* __restrict__ means, const float* __restrict__ sca
             rec.y1 = (int16_t)fp.py1;
         }
     }
-    records[r] = rec;
     tiles_touched[r] = count;
+    if (count == 0u) return;   // no list refers to this record: neither it nor its cache is read
+    records[r] = rec;
     if (count <= 3u)
         tile_cache[r] = make_uint4(g.zkey, ids[0], ids[1], ids[2]);
     else if (count <= (uint32_t)FS_INLINE_TILES && fits)
