@@ -4,6 +4,8 @@
 // One lane per (view, surfel); 256-lane workgroups, grid.y = view.  Geometry
 // runs in double precision (gfx950 runs fp64 at the fp32 vector rate), so the
 // tile count is the exact per-pixel footprint count.
+#include <cmath>
+
 #include "fs_internal.h"
 
 static_assert(FS_INLINE_TILES == 8 && FS_TILE_CACHE_WORDS == 4, "the cache is one uint4 per record");
@@ -12,16 +14,72 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// at least four waves per SIMD (128 VGPRs): the double-precision sweep is
-// latency-bound and needs the occupancy
+// Conservative view test before the double-precision projection.  The cutoff
+// disk (semi-axes k r_u, k r_v in the tangent plane, k^2 = 2 ln(o / alpha_min))
+// lies inside the ball of radius rho = kmax max(r_u, r_v) around the centre,
+// kmax = sqrt(2 ln(1 / alpha_min)) >= k for o <= 1.  If that ball is in front
+// of the near plane and beyond one side plane of the image's frustum (x < 0,
+// x > W, y < 0 or y > H for every point), no pixel centre can be in the
+// footprint: the surfel has no tiles, whatever the full path would compute
+// near the threshold (the centres are at least half a pixel inside).  Planes
+// through the camera centre, e.g. fx X + cx Z < 0 for x < 0; |n| is bounded
+// by the sum of the absolute components.  Anything the test cannot decide
+// (o > 1, non-finite input, a ball reaching the near plane) takes the full path.
+FS_DEV bool fs_outside_view(const float* pm, const float* ps, float op, const fs_camera& cam, double kmax) {
+    if (!(op <= 1.f)) return false;
+    const double p0 = pm[0], p1 = pm[1], p2 = pm[2];
+    const double s0 = ps[0], s1 = ps[1];
+    double pc[3];
+    for (int r = 0; r < 3; ++r)
+        pc[r] = (((double)cam.R[3 * r] * p0 + (double)cam.R[3 * r + 1] * p1) + (double)cam.R[3 * r + 2] * p2) +
+                (double)cam.t[r];
+    const double rho = kmax * (s0 > s1 ? s0 : s1) * (1.0 + 1e-6) + 1e-9 * (fabs(pc[0]) + fabs(pc[1]) + fabs(pc[2]));
+    if (!(rho >= 0.0) || !(pc[2] - rho > (double)cam.z_near)) return false;
+    const double fx = cam.fx, fy = cam.fy, cx = cam.cx, cy = cam.cy, W = cam.width, H = cam.height;
+    const double xl = fx * pc[0] + cx * pc[2], xr = fx * pc[0] + (cx - W) * pc[2];
+    const double yt = fy * pc[1] + cy * pc[2], yb = fy * pc[1] + (cy - H) * pc[2];
+    return xl + rho * (fabs(fx) + fabs(cx)) < 0.0 || xr - rho * (fabs(fx) + fabs(cx - W)) > 0.0 ||
+           yt + rho * (fabs(fy) + fabs(cy)) < 0.0 || yb - rho * (fabs(fy) + fabs(cy - H)) > 0.0;
+}
+
+// Each workgroup first runs the view test on its kThreads surfels, then
+// packs the undecided ones into its first waves (in surfel order) so that
+// the double-precision path runs on full waves and the waves left without
+// a surfel end at once; every surfel still writes only its own outputs.
+// At least four waves per SIMD (128 VGPRs): the double-precision work is
+// latency-bound and needs the occupancy.
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 preprocess_kernel(const float* __restrict__ means, const float* __restrict__ scales, const float* __restrict__ quats,
                   const float* __restrict__ opacity, int64_t n, const fs_camera* __restrict__ cams, fs_opts o,
-                  FsRecord* __restrict__ records, uint32_t* __restrict__ tiles_touched, uint4* __restrict__ tile_cache) {
+                  FsRecord* __restrict__ records, uint32_t* __restrict__ tiles_touched, uint4* __restrict__ tile_cache,
+                  double kmax) {
+    __shared__ uint32_t s_cand[kThreads];
+    __shared__ int s_count[kThreads / 64];
     const int v = blockIdx.y;
-    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
+    const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t i0 = (int64_t)blockIdx.x * kThreads;
     const fs_camera cam = cams[v];
+    bool cand = false;
+    if (i0 + tid < n) {
+        const int64_t k = i0 + tid;
+        if (fs_outside_view(means + 3 * k, scales + 2 * k, opacity[k], cam, kmax))
+            tiles_touched[(int64_t)v * n + k] = 0u;   // nothing else is written for a surfel without tiles
+        else
+            cand = true;
+    }
+    const uint64_t m = __ballot(cand);
+    if (lane == 0) s_count[wave] = __popcll(m);
+    __syncthreads();
+    int before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        before += w < wave ? s_count[w] : 0;
+        total += s_count[w];
+    }
+    if (cand) s_cand[before + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)tid;
+    __syncthreads();
+    if (tid >= total) return;
+    const int64_t i = i0 + s_cand[tid];
     const int64_t r = (int64_t)v * n + i;
     FsRecord rec;
     rec.h0 = rec.h1 = rec.h2 = 0.0;
@@ -124,7 +182,9 @@ hipError_t fs_launch_preprocess(const float* means, const float* scales, const f
                                 FsRecord* records, uint32_t* tiles_touched, uint32_t* tile_cache, hipStream_t s) {
     if (n == 0) return hipSuccess;
     dim3 grid((unsigned)((n + kThreads - 1) / kThreads), (unsigned)num_views);
+    // bound on the cutoff radius k for opacities <= 1, widened against rounding
+    const double kmax = std::sqrt(2.0 * std::log(1.0 / (double)o.alpha_min)) * (1.0 + 1e-9);
     hipLaunchKernelGGL(preprocess_kernel, grid, dim3(kThreads), 0, s, means, scales, quats, opacity, n, cams, o,
-                       records, tiles_touched, reinterpret_cast<uint4*>(tile_cache));
+                       records, tiles_touched, reinterpret_cast<uint4*>(tile_cache), kmax);
     return hipGetLastError();
 }
