@@ -234,6 +234,30 @@ def needle_scene(n: int = 400, *, seed: int = 5) -> tuple[Scene, Camera]:
     return Scene(means, scales, quats, opacity, feats), centred_camera(512, 128)
 
 
+def border_scene(n: int = 3000, *, seed: int = 3) -> tuple[Scene, Camera]:
+    """Surfels centred just outside (or just inside) the four edges of a
+    160x96 view, by -0.5 to 1.5 times their approximate projected cutoff
+    radius: many reach into the image with their centre outside it, many
+    miss it by a little (the cases a view test before projection must get
+    right)."""
+    rng = np.random.default_rng(seed)
+    cam = centred_camera(160, 96)
+    z = rng.uniform(2.0, 6.0, n)
+    s = np.exp(rng.uniform(np.log(0.01), np.log(0.08), n))
+    rpx = np.sqrt(2.0 * np.log(0.9 * 255.0)) * s * cam.fx / z
+    side = rng.integers(0, 4, n)
+    t = rng.uniform(0.0, 1.0, n)
+    off = rng.uniform(-0.5, 1.5, n) * rpx
+    px = np.where(side == 0, -off, np.where(side == 1, cam.width + off, t * cam.width))
+    py = np.where(side == 2, -off, np.where(side == 3, cam.height + off, t * cam.height))
+    means = np.stack([(px - cam.cx) * z / cam.fx, (py - cam.cy) * z / cam.fy, z], 1).astype(np.float32)
+    q = rng.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    scales = np.stack([s, s * rng.uniform(0.3, 1.0, n)], 1).astype(np.float32)
+    feats = rng.standard_normal((n, 4)).astype(np.float32)
+    return Scene(means, scales, q.astype(np.float32), np.full(n, 0.9, np.float32), feats), cam
+
+
 def parity_small(seed: int = 0) -> tuple[Scene, Camera]:
     """2,000 surfels, 128x128, RGB + 16 feature channels (C = 19)."""
     return uniform_scene(2000, seed=seed), centred_camera(128, 128)

@@ -306,3 +306,20 @@ def test_sparse_footprints_pairs_and_image():
     ref = oracle.render_scene(scene, cam, kcap=256)
     rast, fr = _render(scene, cam, tile=8)
     check_image(fr, ref, rast, 0, scene.channels, 0, "needles")
+
+
+def test_border_surfels_pairs_and_image():
+    """Surfels centred just outside and just inside the image edges: the
+    view test that precedes the projection must never drop one that reaches
+    a pixel centre.  Pairs bit-exact (tiles 8 and 16, both tile modes) and
+    the full blend within tolerance."""
+    _print_case("border surfels")
+    scene, cam = scenes.border_scene()
+    for tile in (8, 16):
+        _, fr = _render(scene, cam, tile=tile)
+        assert check_pairs(fr, scene, cam, tile) > 1000
+    rast, fr = _render(scene, cam, tile=8, tile_mode="bbox")
+    rast_p, fr_p = _render(scene, cam, tile=8)
+    assert torch.equal(fr.feat, fr_p.feat) and torch.equal(fr.n, fr_p.n)
+    ref = oracle.render_scene(scene, cam, kcap=256)
+    check_image(fr_p, ref, rast_p, 0, scene.channels, 0, "border")

@@ -402,3 +402,20 @@ def test_needle_scene_has_sparse_footprints():
     sparse = (counts >= 4) & (counts <= 8) & (span > 15)
     assert sparse.sum() >= 50
     assert (counts > 8).sum() >= 3 and ((counts >= 1) & (counts <= 3)).sum() >= 3
+
+
+def test_border_scene_has_outside_centres_with_tiles():
+    """The border workload of the GPU pair tests holds surfels whose centre
+    is outside the image yet whose footprint covers pixel centres, and
+    surfels just outside that cover none."""
+    from paper_2604_10951_amd import scenes
+    scene, cam = scenes.border_scene()
+    proj = oracle.project_scene(scene, cam)
+    counts, flags, _, _ = oracle.tile_sets(proj, cam.width, cam.height, 8)
+    assert (flags != 0).sum() == 0
+    m = scene.means.astype(np.float64)
+    px = cam.fx * m[:, 0] / m[:, 2] + cam.cx
+    py = cam.fy * m[:, 1] / m[:, 2] + cam.cy
+    outside = (px < 0) | (px > cam.width) | (py < 0) | (py > cam.height)
+    assert (outside & (counts > 0)).sum() >= 300
+    assert (outside & (counts == 0)).sum() >= 300
