@@ -12,8 +12,10 @@
 //      cursor (any order inside the tile);
 //   2. a sort of every tile's run by (depth key, record), as 64-bit composite
 //      keys: runs of up to kWaveCap entries by one wave each (bitonic network
-//      in the wave's registers), up to kLargeCap by a workgroup (bitonic in
-//      64 KB of LDS), longer runs by a stable one-workgroup LSD radix sort
+//      in the wave's registers), up to kMergeCap by a workgroup (waves sort
+//      512-entry chunks in registers, then pairwise merges in LDS), up to
+//      kLargeCap by a workgroup bitonic network in 64 KB of LDS, longer runs
+//      by a stable one-workgroup LSD radix sort
 //      through global memory.
 // Every launch is sized from the capacity, not from the device-side pair
 // count, so the sequence can be captured in a graph.
@@ -24,6 +26,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kWaveCap = 512;     // entries per run sorted by one wave (8 per lane, in registers)
 constexpr int kLargeCap = 8192;   // entries per run sorted in LDS by a workgroup (64 KB)
+constexpr int kMergeCap = 4096;   // entries per run sorted by chunk sorts and merges (two 32 KB buffers)
 constexpr int kLdsTiles = 16384;  // tile counts kept in LDS by the count and scatter kernels
 constexpr int kChunk = 8192;      // pairs per workgroup in the count and scatter kernels
 constexpr int kChunkThreads = 1024;
@@ -266,17 +269,10 @@ FS_DEV void sort_run_lds(uint64_t* s, const uint2* __restrict__ in, uint64_t til
 // fetched by a shuffle.  The network is the textbook one (stage k, distance
 // j, ascending where i & k == 0), so the result is the sorted run.
 template <int LOGE>
-FS_DEV void sort_run_wave(const uint2* __restrict__ in, uint64_t tile, uint32_t start, int n,
-                          uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+FS_DEV void wave_network(uint64_t (&x)[1 << LOGE]) {
     constexpr int E = 1 << LOGE;
     constexpr int LOGN = 6 + LOGE;
     const int lane = (int)threadIdx.x & 63;
-    uint64_t x[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = lane * E + e;
-        x[e] = i < n ? composite(in[start + i]) : ~0ull;
-    }
 #pragma unroll
     for (int lk = 1; lk <= LOGN; ++lk) {
         const int k = 1 << lk;
@@ -306,6 +302,20 @@ FS_DEV void sort_run_wave(const uint2* __restrict__ in, uint64_t tile, uint32_t 
             }
         }
     }
+}
+
+template <int LOGE>
+FS_DEV void sort_run_wave(const uint2* __restrict__ in, uint64_t tile, uint32_t start, int n,
+                          uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    constexpr int E = 1 << LOGE;
+    const int lane = (int)threadIdx.x & 63;
+    uint64_t x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = lane * E + e;
+        x[e] = i < n ? composite(in[start + i]) : ~0ull;
+    }
+    wave_network<LOGE>(x);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int i = lane * E + e;
@@ -313,6 +323,69 @@ FS_DEV void sort_run_wave(const uint2* __restrict__ in, uint64_t tile, uint32_t 
             keys[start + i] = (tile << 32) | (x[e] >> 32);
             vals[start + i] = (uint32_t)x[e];
         }
+    }
+}
+
+// Sort of one run of kWaveCap < n <= kMergeCap entries by the workgroup:
+// wave w sorts entries [512 w, 512 w + 512) of the run in registers (padding
+// = ~0, which sorts last), then runs of 512, 1024, ... are merged pairwise
+// through LDS, ping-ponging between the two halves of s.  Every thread
+// makes 8 outputs per round: it finds, by binary search along the merge
+// path, how many of its first output's predecessors come from the left run
+// (keys are distinct), then merges 8 entries.  At most three rounds.
+FS_DEV void sort_run_merge(uint64_t* s, const uint2* __restrict__ in, uint64_t tile, uint32_t start, int n,
+                           uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    static_assert(kLongThreads * 8 >= kMergeCap && 2 * kMergeCap <= kLargeCap, "buffers of the merge rounds");
+    const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = (n + kWaveCap - 1) / kWaveCap;   // sorted chunks, 2 .. kMergeCap / kWaveCap
+    const int N = m * kWaveCap;
+    uint64_t* a = s;
+    uint64_t* b = s + kMergeCap;
+    if (wave < m) {
+        uint64_t x[8];
+        const int base = wave * kWaveCap + lane * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = base + e < n ? composite(in[start + base + e]) : ~0ull;
+        wave_network<3>(x);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a[base + e] = x[e];
+    }
+    __syncthreads();
+    for (int width = kWaveCap; width < N; width *= 2) {
+        const int o = tid * 8;   // first output of this thread
+        if (o < N) {
+            const int ps = (o / (2 * width)) * (2 * width);
+            const int na = N - ps < width ? N - ps : width;
+            const int nb = N - ps - na < width ? N - ps - na : width;
+            const uint64_t* A = a + ps;
+            const uint64_t* B = A + na;
+            const int d = o - ps;
+            int lo = d - nb > 0 ? d - nb : 0, hi = d < na ? d : na;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (A[mid] < B[d - 1 - mid])
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            int i = lo, j = d - lo;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const bool take_a = j >= nb || (i < na && A[i] < B[j]);
+                b[o + e] = take_a ? A[i] : B[j];
+                i += take_a ? 1 : 0;
+                j += take_a ? 0 : 1;
+            }
+        }
+        __syncthreads();
+        uint64_t* t = a;
+        a = b;
+        b = t;
+    }
+    for (int i = tid; i < n; i += kLongThreads) {
+        const uint64_t c = a[i];
+        keys[start + i] = (tile << 32) | (c >> 32);
+        vals[start + i] = (uint32_t)c;
     }
 }
 
@@ -421,7 +494,9 @@ FS_DEV void sort_run_global(uint2* a, uint2* b, uint64_t tile, uint32_t start, u
 
 // Runs longer than kWaveCap, from the list: up to kLargeCap entries by a
 // workgroup bitonic network in LDS, longer ones by the global radix sort.
-__global__ void __launch_bounds__(kLongThreads)
+// Two workgroups per CU (64 VGPRs at most) keep every long run of a frame
+// in flight at once.
+__global__ void __launch_bounds__(kLongThreads) __attribute__((amdgpu_waves_per_eu(8)))
 sort_long_runs_kernel(uint2* __restrict__ in, const uint32_t* __restrict__ ranges,
                       const uint32_t* __restrict__ long_list, const uint32_t* __restrict__ long_count,
                       uint64_t* keys, uint32_t* __restrict__ vals) {
@@ -431,7 +506,9 @@ sort_long_runs_kernel(uint2* __restrict__ in, const uint32_t* __restrict__ range
         const uint64_t t = long_list[it];
         const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
         const uint32_t n = end - start;
-        if (n <= (uint32_t)kLargeCap) {
+        if (n <= (uint32_t)kMergeCap) {
+            sort_run_merge(s, in, t, start, (int)n, keys, vals);
+        } else if (n <= (uint32_t)kLargeCap) {
             sort_run_lds<kLongThreads>(s, in, t, start, (int)n, keys, vals);
         } else {
             // the run's own slice of the key array is the radix passes' second
