@@ -205,8 +205,26 @@ sort_scatter_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restric
         if (t < (uint64_t)tiles) atomicAdd(&h[t], 1u);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < T; i += kChunkThreads)
-        if (h[i]) h[i] = ranges[2 * i] + atomicAdd(&fill[i], h[i]);   // first position of this chunk's run
+    // first position of this chunk's run in every tile it touches: the
+    // (memory-side) reservations of a thread are independent, so all are
+    // issued before the first result is waited for
+    static_assert(kLdsTiles % kChunkThreads == 0, "whole rounds of bins");
+    constexpr int kRounds = kLdsTiles / kChunkThreads;
+    uint32_t cnt[kRounds], got[kRounds], first[kRounds];
+#pragma unroll
+    for (int k = 0; k < kRounds; ++k) {
+        const int i = (int)threadIdx.x + k * kChunkThreads;
+        cnt[k] = i < T ? h[i] : 0u;
+        got[k] = 0u;
+        first[k] = 0u;
+        if (cnt[k] != 0u) {
+            got[k] = atomicAdd(&fill[i], cnt[k]);
+            first[k] = ranges[2 * i];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kRounds; ++k)
+        if (cnt[k] != 0u) h[(int)threadIdx.x + k * kChunkThreads] = first[k] + got[k];
     __syncthreads();
     for (int64_t i = c0 + threadIdx.x; i < c1; i += kChunkThreads) {
         const uint64_t k = keys[i];
