@@ -456,7 +456,7 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
     __shared__ uint2 s_pairs[64 * KC];   // the block's compact lists (K <= KC)
     __shared__ int s_cnt[64];
     __shared__ int s_off[64];                  // first pair of each pixel's list
-    __shared__ uint32_t s_rowid[W];
+    __shared__ uint32_t s_rowid[64 * KC];         // the block's row list (R <= 64 K)
     const int tid = (int)threadIdx.x;
     const int64_t block = xcd_remap(blockIdx.x, nblocks);
     const BlockPos bp = locate_block(block, S, 8, cams, num_views);
@@ -468,7 +468,7 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
     const uint32_t nr = nrows[block];
     const uint32_t R = nr & 0xffffu, NP = nr >> 16;   // rows and listed pairs of the block
     const uint32_t* __restrict__ rowlist = rows + block * 64 * (int64_t)K;
-    // lists, counts and the first window's row ids: one round trip (a block
+    // lists, counts and the row list: one round trip (a block
     // no pixel of which blends anything has R = 0 and only writes zeros)
     if (R > 0)
         for (int t = tid; t < (int)NP; t += kGatherThreads) s_pairs[t] = pairs[block * 64 * (int64_t)K + t];
@@ -476,7 +476,7 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
         const int px = bp.x0 + (tid & 7), py = bp.y0 + (tid >> 3);
         s_cnt[tid] = (px < cam.width && py < cam.height) ? counts[cam.pixel_offset + (int64_t)py * cam.width + px] : 0;
     }
-    if (tid < W && (uint32_t)tid < R) s_rowid[tid] = rowlist[tid];
+    for (int t = tid; t < (int)R; t += kGatherThreads) s_rowid[t] = rowlist[t];
     float acc[kPasses][VE];
     int cur[kPasses];
 #pragma unroll
@@ -505,7 +505,7 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
             const int v = i0 + (tid & 63);
             if (v < nvec) {
                 const int r = v / nv, c = v - r * nv;
-                const FT* src = feats + (int64_t)s_rowid[r] * C + c * VE;
+                const FT* src = feats + (int64_t)s_rowid[s0 + r] * C + c * VE;
                 __builtin_amdgcn_global_load_lds((const void*)src,
                                                  (__attribute__((address_space(3))) void*)&s_rows[i0], 16, 0, 0);
             }
@@ -532,11 +532,7 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
             }
             cur[k] = j;
         }
-        if (s0 + W < R) {
-            __syncthreads();   // the window is consumed
-            if (tid < W && s0 + W + (uint32_t)tid < R) s_rowid[tid] = rowlist[s0 + W + tid];
-            __syncthreads();
-        }
+        if (s0 + W < R) __syncthreads();   // the window is consumed
     }
 #pragma unroll
     for (int k = 0; k < kPasses; ++k) {
