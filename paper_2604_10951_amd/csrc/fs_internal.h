@@ -529,6 +529,17 @@ FS_DEV int64_t xcd_remap(int64_t g, int64_t G) {
     return (g % 8) * per + g / 8;
 }
 
+// Workgroup -> work item in chunks: the XCDs take turns with runs of `chunk`
+// consecutive items (chunk i goes to XCD i mod 8), so all XCDs sweep the
+// work in step while neighbouring items still share an XCD.  Items past the
+// last whole round of 8 chunks keep their own index.
+FS_DEV int64_t xcd_remap_chunked(int64_t g, int64_t G, int64_t chunk) {
+    const int64_t round = 8 * chunk;
+    if (g >= (G / round) * round) return g;
+    const int64_t x = g % 8, s = g / 8;   // XCD and its s-th workgroup
+    return ((s / chunk) * 8 + x) * chunk + s % chunk;
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launch helpers implemented in the .hip files.
 // ---------------------------------------------------------------------------
