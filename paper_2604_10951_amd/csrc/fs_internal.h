@@ -540,6 +540,15 @@ FS_DEV int64_t xcd_remap_chunked(int64_t g, int64_t G, int64_t chunk) {
     return ((s / chunk) * 8 + x) * chunk + s % chunk;
 }
 
+// 8x8 blocks in one tile row of the first view: the chunk the block passes
+// hand to the XCDs in turn (measured best on 1280- and 640-pixel views
+// against smaller and larger chunks and against one run per XCD).
+FS_DEV int64_t block_row_chunk(const fs_camera* cams, int S) {
+    const int64_t tiles_x = ((int64_t)cams[0].width + S - 1) / S;
+    const int64_t sb = S / 8;
+    return tiles_x * sb * sb;
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launch helpers implemented in the .hip files.
 // ---------------------------------------------------------------------------

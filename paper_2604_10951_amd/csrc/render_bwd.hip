@@ -423,7 +423,7 @@ topk_grad_kernel(const FsRecord* __restrict__ records, const uint2* __restrict__
     __shared__ int s_wave[kGradThreads / 64];
     __shared__ float s_grec[kGradSlots][10];   // dL/dL and dL/do of the first kGradSlots row slots
     const int tid = (int)threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t block = xcd_remap(blockIdx.x, nblocks);
+    const int64_t block = xcd_remap_chunked(blockIdx.x, nblocks, block_row_chunk(cams, S));
     const BlockPos bp = locate_block(block, S, 8, cams, num_views);
     if (!bp.valid) return;           // uniform
     const uint32_t R = nrows[block] & 0xffffu;   // rows (the high half counts the listed pairs)

@@ -17,20 +17,16 @@
 // C floats per pixel) dominates its traffic, and the rows it reads are shared
 // by neighbouring pixels and served mostly by L2.
 //
-// Both launches hand the XCDs runs of consecutive blocks in turn
+// Both launches hand the XCDs one tile row of blocks each in turn
 // (neighbouring tiles share surfels, so their records and rows stay in that
-// XCD's L2, while every XCD gets its share of the dense regions).
+// XCD's L2, while every XCD gets its share of the dense regions; one
+// contiguous eighth of the image per XCD left the XCDs holding the dense
+// bands last: render 216 vs 209 us on the 1280x720 frame).
 #include "fs_internal.h"
 
 namespace {
 
 constexpr int kSelBatch = 32;   // list entries staged per step in the selection pass
-// Blocks per XCD turn in both passes: neighbouring blocks share an XCD's L2
-// while all XCDs move through the image together, so a dense region is
-// spread over the XCDs (one XCD per contiguous eighth of the image left the
-// XCDs holding the dense bands last: 216 vs 208 us for the 1280x720 frame;
-// chunks of 40, 80 and 480 blocks measured 219, 210 and 215 us).
-constexpr int64_t kXcdChunk = 160;
 constexpr int kGatherThreads = 256;
 constexpr int kGatherUnroll = 8;  // (surfel, weight) pairs whose row loads are in flight together
 constexpr int kStagedK = 16;      // largest K of the staged gather (its lists live in LDS)
@@ -68,7 +64,7 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
     constexpr int kRecSlots = (BG * kQ + 63) / 64;    // record float4 per lane
     __shared__ SelShared<KC> sm;
     const int lane = threadIdx.x;
-    const int64_t block = xcd_remap_chunked(blockIdx.x, nblocks, kXcdChunk);
+    const int64_t block = xcd_remap_chunked(blockIdx.x, nblocks, block_row_chunk(cams, S));
     const BlockPos bp = locate_block(block, S, 8, cams, num_views);
     if (!bp.valid) return;   // uniform across the wave
     const fs_camera& cam = cams[bp.view];
@@ -464,7 +460,7 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
     __shared__ int s_off[64];                  // first pair of each pixel's list
     __shared__ uint32_t s_rowid[64 * KC];         // the block's row list (R <= 64 K)
     const int tid = (int)threadIdx.x;
-    const int64_t block = xcd_remap_chunked(blockIdx.x, nblocks, kXcdChunk);
+    const int64_t block = xcd_remap_chunked(blockIdx.x, nblocks, block_row_chunk(cams, S));
     const BlockPos bp = locate_block(block, S, 8, cams, num_views);
     if (!bp.valid) return;   // uniform over the workgroup
     const fs_camera& cam = cams[bp.view];
