@@ -311,7 +311,13 @@ render_fwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
                   const uint32_t* __restrict__ order, uint32_t* __restrict__ ticket, uint32_t nblocks) {
     __shared__ FwdShared<CPL, FT, WAVES, BG> sm;
     if (order == nullptr) {
-        render_block<CPL, FT, WAVES, BG, VEC>(blockIdx.x, sm, records, vals, ranges, feats, C, n, num_records, cams,
+        // the XCDs take one tile row of blocks each in turn: neighbouring
+        // blocks share an L2 and dense regions are spread over all XCDs
+        // (full blend of the 1280x720 frame: 1.77 -> 1.41 ms)
+        constexpr int RBv = WAVES == 1 ? 8 : 16;
+        const int64_t tiles_x = ((int64_t)cams[0].width + S - 1) / S, sb = S / RBv;
+        const int64_t blk = xcd_remap_chunked(blockIdx.x, gridDim.x, tiles_x * sb * sb);
+        render_block<CPL, FT, WAVES, BG, VEC>(blk, sm, records, vals, ranges, feats, C, n, num_records, cams,
                                               num_views, S, o, out_feat, out_T, out_n, out_last, out_idx, counters);
         return;
     }
