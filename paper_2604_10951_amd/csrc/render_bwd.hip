@@ -89,9 +89,11 @@ render_bwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
     __shared__ float s_grec[BG][kGradFloats];
 
     const int lane = threadIdx.x;
-    // block position (8x8 pixels inside a binning tile)
+    // block position (8x8 pixels inside a binning tile); the XCDs take one
+    // tile row of blocks each in turn (4.38 -> 3.99 ms on the 640x480
+    // full-blend backward)
     const int sb = S / 8;
-    const int64_t b = blockIdx.x;
+    const int64_t b = xcd_remap_chunked(blockIdx.x, gridDim.x, block_row_chunk(cams, S));
     const int64_t tile = b / (sb * sb);
     const int sub = (int)(b % (sb * sb));
     const int v = fs_view_of_tile(cams, num_views, tile);
