@@ -66,11 +66,12 @@ def test_batched_views_equal_single_views_and_oracle():
         check_image(fr, ref, rast, v, scene.channels, 6, f"view {v}")
 
 
-def test_graph_replay_matches_eager_and_follows_camera_updates():
-    _case("graph replay")
+@pytest.mark.parametrize("schedule", ["persistent", "split"])
+def test_graph_replay_matches_eager_and_follows_camera_updates(schedule):
+    _case(f"graph replay ({schedule})")
     scene, cams = _views_small()
     tens = raster.scene_tensors(scene, _dev())
-    rast = raster.Rasterizer(cams, tile=8, topk=4, schedule="persistent", device=_dev())
+    rast = raster.Rasterizer(cams, tile=8, topk=4, schedule=schedule, device=_dev())
     graph = raster.FrameGraph(rast, tens)
     eager = raster.Rasterizer(cams, tile=8, topk=4, device=_dev())
     ref = _frame(eager, tens)
