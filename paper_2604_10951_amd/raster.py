@@ -66,7 +66,7 @@ class Rasterizer:
 
     def __init__(self, cams, *, tile: int = 16, topk: int = 0, tile_mode: str = "precise",
                  feat_dtype: str = "f32", alpha_min: float = ALPHA_MIN, alpha_max: float = ALPHA_MAX,
-                 t_stop: float = T_STOP, batch: int = 0, schedule: str = "grid",
+                 t_stop: float = T_STOP, batch: int = 0, schedule: str = "auto",
                  device: str | torch.device = "cuda", pair_capacity: int = 0):
         self.lib = L.load()
         self.device = torch.device(device)
@@ -75,6 +75,8 @@ class Rasterizer:
         mode = {"precise": L.FS_TILES_PRECISE, "bbox": L.FS_TILES_BBOX}[tile_mode]
         dt = {"f32": L.FS_FEAT_F32, "bf16": L.FS_FEAT_BF16}[feat_dtype]
         self.feat_dtype = feat_dtype
+        if schedule == "auto":   # the measured fastest: split for Top-K, the fused grid for the full blend
+            schedule = "split" if topk > 0 else "grid"
         sched = {"grid": L.FS_SCHED_GRID, "persistent": L.FS_SCHED_PERSISTENT, "split": L.FS_SCHED_SPLIT}[schedule]
         self.opts = L.make_opts(tile, topk, mode, dt, alpha_min, alpha_max, t_stop, batch, sched)
         self.cam_arr, self.total_tiles, self.total_pixels = L.make_cameras(self.cams, tile)

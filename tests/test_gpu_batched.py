@@ -41,7 +41,8 @@ def test_persistent_schedule_is_bit_identical(tile, batch):
     _case(f"persistent tile={tile} batch={batch}")
     scene, cams = _views_small()
     tens = raster.scene_tensors(scene, _dev())
-    a = _frame(raster.Rasterizer(cams, tile=tile, batch=batch, topk=5, device=_dev()), tens, want_idx=True)
+    a = _frame(raster.Rasterizer(cams, tile=tile, batch=batch, topk=5, schedule="grid", device=_dev()), tens,
+               want_idx=True)
     b = _frame(raster.Rasterizer(cams, tile=tile, batch=batch, topk=5, schedule="persistent", device=_dev()), tens,
                want_idx=True)
     for name in ("feat", "T", "n", "idx"):

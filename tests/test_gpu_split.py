@@ -53,7 +53,7 @@ def test_split_bit_identical_to_fused(C_extra, tile, K, dtype):
     scene = scenes.uniform_scene(2500, seed=21, feat_channels=C_extra)
     cams = [scenes.centred_camera(101, 77), scenes.lookat_camera([0.4, -0.2, -1.0], [0, 0, 4], 80, 72)]
     tens = raster.scene_tensors(scene, _dev(), dtype)
-    _, a = _frame(cams, tens, tile=tile, topk=K, feat_dtype=dtype)
+    _, a = _frame(cams, tens, tile=tile, topk=K, feat_dtype=dtype, schedule="grid")
     _, b = _frame(cams, tens, tile=tile, topk=K, feat_dtype=dtype, schedule="split")
     assert int(a.n.sum()) > 1000
     _same(a, b)
@@ -98,7 +98,7 @@ def test_split_many_rows_per_block(K, dtype, C_extra):
     scene = scenes.uniform_scene(40000, seed=4, scale_range=(0.003, 0.01), feat_channels=C_extra)
     cam = scenes.centred_camera(64, 48)
     tens = raster.scene_tensors(scene, _dev(), dtype)
-    _, a = _frame([cam], tens, tile=8, topk=K, feat_dtype=dtype)
+    _, a = _frame([cam], tens, tile=8, topk=K, feat_dtype=dtype, schedule="grid")
     rast, b = _frame([cam], tens, tile=8, topk=K, feat_dtype=dtype, schedule="split")
     counters = torch.zeros(4, dtype=torch.int64, device=_dev())
     rast.render_forward(tens[4], counters=counters)
