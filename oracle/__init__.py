@@ -218,7 +218,9 @@ def _render_common(proj, feats, opacity):
 
 def render_image(proj: Projection, opacity, feats, width: int, height: int, *, K: int = 0, kcap: int | None = None,
                  alpha_min: float = ALPHA_MIN, alpha_max: float = ALPHA_MAX, t_stop: float = T_STOP,
-                 prefilter: bool = True) -> Render:
+                 prefilter: bool = True, by_weight: bool = False) -> Render:
+    """Whole-image render; with by_weight (K > 0) the K contributors of largest
+    weight of the full walk are blended instead of the first K."""
     lib = load()
     feats, opacity, H = _render_common(proj, feats, opacity)
     n, C = feats.shape
@@ -233,7 +235,7 @@ def render_image(proj: Projection, opacity, feats, width: int, height: int, *, K
     ncl = np.zeros(npix, np.int32)
     rc = lib.fso_render_image(_ptr(proj.valid, _i32), _ptr(proj.zkey, _u32), _ptr(H, _d), _ptr(proj.k2, _d),
                               _ptr(opacity, _d), _ptr(feats, _d), n, C, width, height, int(prefilter), alpha_min,
-                              alpha_max, t_stop, K, kcap, _ptr(F, _d), _ptr(absF, _d), _ptr(T, _d),
+                              alpha_max, t_stop, -K if by_weight else K, kcap, _ptr(F, _d), _ptr(absF, _d), _ptr(T, _d),
                               _ptr(nout, _i32), _ptr(idx, _i32), _ptr(amb, _i32), _ptr(ncl, _i32))
     if rc != 0:
         raise MemoryError("oracle render_image failed")
@@ -243,7 +245,8 @@ def render_image(proj: Projection, opacity, feats, width: int, height: int, *, K
 
 
 def render_pixels(proj: Projection, opacity, feats, width: int, pix, *, K: int = 0, kcap: int | None = None,
-                  alpha_min: float = ALPHA_MIN, alpha_max: float = ALPHA_MAX, t_stop: float = T_STOP) -> Render:
+                  alpha_min: float = ALPHA_MIN, alpha_max: float = ALPHA_MAX, t_stop: float = T_STOP,
+                  by_weight: bool = False) -> Render:
     """Brute-force render of selected pixels (pix = py * width + px)."""
     lib = load()
     feats, opacity, H = _render_common(proj, feats, opacity)
@@ -260,17 +263,18 @@ def render_pixels(proj: Projection, opacity, feats, width: int, pix, *, K: int =
     ncl = np.zeros(m, np.int32)
     lib.fso_render_pixels(_ptr(proj.valid, _i32), _ptr(proj.zkey, _u32), _ptr(H, _d), _ptr(proj.k2, _d),
                           _ptr(opacity, _d), _ptr(feats, _d), n, C, width, _ptr(pix, _i64), m, alpha_min, alpha_max,
-                          t_stop, K, kcap, _ptr(F, _d), _ptr(absF, _d), _ptr(T, _d), _ptr(nout, _i32),
+                          t_stop, -K if by_weight else K, kcap, _ptr(F, _d), _ptr(absF, _d), _ptr(T, _d), _ptr(nout, _i32),
                           _ptr(idx, _i32), _ptr(amb, _i32), _ptr(ncl, _i32))
     return Render(F, absF, T, nout, idx[:, :kcap], amb, ncl)
 
 
 def render_scene(scene, cam, *, K: int = 0, kcap: int | None = None, alpha_min: float = ALPHA_MIN,
                  alpha_max: float = ALPHA_MAX, t_stop: float = T_STOP, prefilter: bool = True,
-                 feats=None) -> Render:
+                 feats=None, by_weight: bool = False) -> Render:
     proj = project_scene(scene, cam, alpha_min)
     return render_image(proj, scene.opacity, scene.feats if feats is None else feats, cam.width, cam.height, K=K,
-                        kcap=kcap, alpha_min=alpha_min, alpha_max=alpha_max, t_stop=t_stop, prefilter=prefilter)
+                        kcap=kcap, alpha_min=alpha_min, alpha_max=alpha_max, t_stop=t_stop, prefilter=prefilter,
+                        by_weight=by_weight)
 
 
 @dataclass

@@ -423,9 +423,13 @@ static int cand_cmp(const void* a, const void* b)
 
 typedef struct {
     double alpha_min, alpha_max, t_stop;
-    int K;      /* 0 = blend every accepted surfel */
+    int K;      /* 0 = blend every accepted surfel; < 0: the -K of largest weight */
     int kcap;   /* capacity of the per-pixel index output */
 } blend_opts;
+
+static int blend_pixel_by_weight(const cand_t* cs, int64_t m, const double* k2, const double* opacity,
+                                 const double* feats, int C, int K, const blend_opts* bo, double* F, double* absF,
+                                 double* Tout, int32_t* idx, int32_t* amb, int32_t* nclamp, int32_t* last_cand);
 
 /*
  * Front-to-back blend of one pixel over its candidates sorted by depth key
@@ -441,6 +445,9 @@ static int blend_pixel(const cand_t* cs, int64_t m, const double* k2, const doub
                        int C, const blend_opts* bo, double* F, double* absF, double* Tout, int32_t* idx,
                        int32_t* amb, int32_t* nclamp, int32_t* last_cand)
 {
+    if (bo->K < 0)
+        return blend_pixel_by_weight(cs, m, k2, opacity, feats, C, -bo->K, bo, F, absF, Tout, idx, amb, nclamp,
+                                     last_cand);
     double T = 1.0;
     int n = 0, a = 0, ncl = 0;
     int32_t lastc = -1;
@@ -477,6 +484,86 @@ static int blend_pixel(const cand_t* cs, int64_t m, const double* k2, const doub
     *nclamp = ncl;
     *last_cand = lastc;
     return n;
+}
+
+typedef struct {
+    double w;
+    int64_t j;
+    uint32_t i;
+} sel_t;
+
+static int weight_cmp(const void* a, const void* b)
+{
+    const sel_t* x = (const sel_t*)a;
+    const sel_t* y = (const sel_t*)b;
+    if (x->w != y->w) return x->w > y->w ? -1 : 1;   /* larger weight first */
+    return x->j < y->j ? -1 : (x->j > y->j ? 1 : 0);  /* then the front one */
+}
+
+static int position_cmp(const void* a, const void* b)
+{
+    const sel_t* x = (const sel_t*)a;
+    const sel_t* y = (const sel_t*)b;
+    return x->j < y->j ? -1 : (x->j > y->j ? 1 : 0);
+}
+
+/*
+ * Top-K by weight (the alternative reading of Sec. 3.4): the whole
+ * front-to-back walk of blend_pixel without the K cutoff gives every
+ * contributor's weight w = alpha T and the final transmittance; the K
+ * contributors with the largest w (equal weights: the front one first) are
+ * blended, front to back, with those weights.  T_final is the walk's.
+ * amb also flags a K-th and (K+1)-th weight within AMBIG_REL of each other.
+ */
+static int blend_pixel_by_weight(const cand_t* cs, int64_t m, const double* k2, const double* opacity,
+                                 const double* feats, int C, int K, const blend_opts* bo, double* F, double* absF,
+                                 double* Tout, int32_t* idx, int32_t* amb, int32_t* nclamp, int32_t* last_cand)
+{
+    double T = 1.0;
+    int a = 0, ncl = 0;
+    int32_t lastc = -1;
+    sel_t* ws = (sel_t*)malloc(sizeof(sel_t) * (size_t)(m > 0 ? m : 1));
+    int64_t nb = 0;
+    for (int c = 0; c < C; ++c) F[c] = absF[c] = 0.0;
+    for (int j = 0; j < bo->kcap; ++j) idx[j] = -1;
+    for (int64_t j = 0; j < m; ++j) {
+        const uint32_t i = cs[j].idx;
+        const double d2 = cs[j].d2;
+        if (fabs(d2 - k2[i]) < AMBIG_REL * k2[i]) a = 1;
+        if (!(d2 <= k2[i])) continue;
+        double alpha = opacity[i] * exp(-0.5 * d2);
+        if (alpha > bo->alpha_max) {
+            alpha = bo->alpha_max;
+            ++ncl;
+        }
+        const double Tn = T * (1.0 - alpha);
+        if (fabs(Tn - bo->t_stop) < AMBIG_REL * bo->t_stop) a = 1;
+        if (Tn < bo->t_stop) break;
+        ws[nb].w = alpha * T;
+        ws[nb].j = j;
+        ws[nb].i = i;
+        ++nb;
+        T = Tn;
+        lastc = (int32_t)j;
+    }
+    qsort(ws, (size_t)nb, sizeof(sel_t), weight_cmp);
+    const int64_t ns = nb < K ? nb : K;
+    if (nb > K && fabs(ws[K - 1].w - ws[K].w) < AMBIG_REL * ws[K - 1].w) a = 1;
+    qsort(ws, (size_t)ns, sizeof(sel_t), position_cmp);
+    for (int64_t s = 0; s < ns; ++s) {
+        const double* c = feats + (int64_t)ws[s].i * C;
+        for (int ch = 0; ch < C; ++ch) {
+            F[ch] += ws[s].w * c[ch];
+            absF[ch] += ws[s].w * fabs(c[ch]);
+        }
+        if (s < bo->kcap) idx[s] = (int32_t)ws[s].i;
+    }
+    free(ws);
+    *Tout = T;
+    *amb = a;
+    *nclamp = ncl;
+    *last_cand = lastc;
+    return (int)ns;
 }
 
 /* Candidate test: every surfel whose d2 is within AMBIG_REL above k2 is kept

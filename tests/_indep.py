@@ -35,10 +35,11 @@ def camera_depth(mean, cam) -> float:
     return float((np.asarray(cam.R, np.float64) @ np.asarray(mean, np.float64) + np.asarray(cam.t, np.float64))[2])
 
 
-def brute_blend(scene, cam, pixels, *, K=0, alpha_min=1 / 255, alpha_max=0.99, t_stop=1e-4):
+def brute_blend(scene, cam, pixels, *, K=0, by_weight=False, alpha_min=1 / 255, alpha_max=0.99, t_stop=1e-4):
     """Pure-Python front-to-back blend (Eq. 2; Top-K of Sec. 3.4 as the first K
-    accepted surfels).  Every surfel is assumed to be in front of the camera.
-    Returns per pixel (F, T, order of contributors)."""
+    accepted surfels, or with by_weight the K contributors of the whole walk
+    with the largest weights alpha T).  Every surfel is assumed to be in front
+    of the camera.  Returns per pixel (F, T, order of contributors)."""
     out = []
     n = scene.means.shape[0]
     z = [np.float32(camera_depth(scene.means[i], cam)) for i in range(n)]
@@ -48,6 +49,7 @@ def brute_blend(scene, cam, pixels, *, K=0, alpha_min=1 / 255, alpha_max=0.99, t
         F = np.zeros(scene.feats.shape[1])
         T = 1.0
         who = []
+        walk = []   # (weight, position, surfel) of every contributor
         for i in order:
             u, v, _ = ray_plane_uv(scene.means[i], scene.scales[i].astype(np.float64), scene.quats[i], cam, x, y)
             o = float(scene.opacity[i])
@@ -56,10 +58,17 @@ def brute_blend(scene, cam, pixels, *, K=0, alpha_min=1 / 255, alpha_max=0.99, t
                 continue
             if T * (1 - alpha) < t_stop:
                 break
-            F += alpha * T * scene.feats[i].astype(np.float64)
+            walk.append((alpha * T, len(walk), i))
+            if not by_weight:
+                F += alpha * T * scene.feats[i].astype(np.float64)
+                who.append(i)
             T *= 1 - alpha
-            who.append(i)
-            if K and len(who) == K:
+            if K and not by_weight and len(who) == K:
                 break
+        if by_weight:
+            top = sorted(walk, key=lambda t: (-t[0], t[1]))[:K] if K else walk
+            for w, _, i in sorted(top, key=lambda t: t[1]):
+                F += w * scene.feats[i].astype(np.float64)
+                who.append(i)
         out.append((F, T, who))
     return out

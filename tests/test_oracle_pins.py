@@ -419,3 +419,62 @@ def test_border_scene_has_outside_centres_with_tiles():
     outside = (px < 0) | (px > cam.width) | (py < 0) | (py > cam.height)
     assert (outside & (counts > 0)).sum() >= 300
     assert (outside & (counts == 0)).sum() >= 300
+
+
+def test_topk_by_weight_two_splats_by_hand():
+    """Top-K by weight (the alternative reading of Sec. 3.4): with a faint
+    splat in front of a strong one, K = 1 keeps the back splat with its
+    weight alpha2 (1 - alpha1), where the first-K reading keeps the front one."""
+    cam = scenes.Camera(8, 8, 8.0, 8.0, 4.0, 4.0)
+    means = [[0.0, 0.0, 4.0], [0.0, 0.0, 2.0]]           # second one is in front
+    sc = scenes.Scene(np.array(means, np.float32), np.array([[0.5, 0.5], [0.25, 0.25]], np.float32),
+                      np.array([[1, 0, 0, 0], [1, 0, 0, 0]], np.float32), np.array([0.9, 0.1], np.float32),
+                      np.array([[0.0, 1.0, 1.0], [1.0, 0.0, 1.0]], np.float32))
+    a_front = float(np.float32(0.1)) * np.exp(-0.25)
+    a_back = float(np.float32(0.9)) * np.exp(-0.25)
+    rw = oracle.render_scene(sc, cam, K=1, by_weight=True)
+    rf = oracle.render_scene(sc, cam, K=1)
+    np.testing.assert_allclose(rw.F[4, 4], a_back * (1 - a_front) * np.array([0.0, 1.0, 1.0]), rtol=1e-12)
+    np.testing.assert_allclose(rf.F[4, 4], a_front * np.array([1.0, 0.0, 1.0]), rtol=1e-12)
+    assert rw.n[4, 4] == 1 and rw.idx[4, 4, 0] == 0 and rf.idx[4, 4, 0] == 1
+    # the walk's transmittance is kept: both contributors were walked
+    assert rw.T[4, 4] == pytest.approx((1 - a_front) * (1 - a_back), rel=1e-12)
+    # K = 2 selects both: the full blend
+    r2 = oracle.render_scene(sc, cam, K=2, by_weight=True)
+    rfull = oracle.render_scene(sc, cam)
+    np.testing.assert_allclose(r2.F[4, 4], rfull.F[4, 4], rtol=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_topk_by_weight_matches_pure_python_brute_force(seed):
+    sc, cam = _tilted_scene(30, 20 + seed)
+    proj = oracle.project_scene(sc, cam)
+    rw = oracle.render_image(proj, sc.opacity, sc.feats, cam.width, cam.height, K=3, by_weight=True)
+    rng = np.random.default_rng(seed)
+    pix = [(int(rng.integers(0, cam.width)), int(rng.integers(0, cam.height))) for _ in range(40)]
+    ref = _indep.brute_blend(sc, cam, pix, K=3, by_weight=True)
+    for (px, py), (F, T, who) in zip(pix, ref):
+        if rw.amb[py, px]:
+            continue
+        np.testing.assert_allclose(rw.F[py, px], F, rtol=1e-9, atol=1e-12)
+        assert rw.T[py, px] == pytest.approx(T, rel=1e-9)
+        assert list(rw.idx[py, px, :rw.n[py, px]]) == who
+
+
+def test_topk_by_weight_invariants():
+    """On the parity scene: K >= contributors equals the full blend; the
+    selected weights sum to at most 1 - T; by weight captures at least the
+    weight the first K capture."""
+    sc, cam = scenes.parity_small()
+    feats = np.concatenate([sc.feats, np.ones((sc.n, 1), np.float32)], 1)   # constant channel: sum of weights
+    proj = oracle.project_scene(sc, cam)
+    full = oracle.render_image(proj, sc.opacity, feats, cam.width, cam.height, kcap=256)
+    big = oracle.render_image(proj, sc.opacity, feats, cam.width, cam.height, K=256, by_weight=True)
+    np.testing.assert_allclose(big.F, full.F, rtol=1e-12, atol=1e-15)
+    for K in (1, 4):
+        rw = oracle.render_image(proj, sc.opacity, feats, cam.width, cam.height, K=K, by_weight=True)
+        rf = oracle.render_image(proj, sc.opacity, feats, cam.width, cam.height, K=K)
+        assert np.all(rw.F[..., -1] <= 1 - rw.T + 1e-12)
+        np.testing.assert_allclose(rw.T, full.T, rtol=1e-12)
+        assert np.all(rw.F[..., -1] >= rf.F[..., -1] - 1e-12)
+        assert np.all(rw.n == np.minimum(K, full.n))
