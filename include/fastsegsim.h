@@ -101,9 +101,17 @@ typedef struct fs_opts {
                             pixel's Top-K (surfel, weight) list to the workspace, then a
                             gather pass blends the feature rows; same results as the
                             other two, bit for bit */
+    int32_t topk_mode;   /* which K surfels a Top-K pixel blends (Sec. 3.4):
+                            FS_TOPK_FIRST: the first K it accepts, front to back;
+                            FS_TOPK_WEIGHT: the K of largest weight alpha T over its
+                            whole front-to-back walk (equal weights: the front one),
+                            blended front to back with those weights; T_final is the
+                            walk's.  FS_TOPK_WEIGHT needs FS_SCHED_SPLIT and topk <= 16
+                            (else FS_ERR_UNSUPPORTED) and has no backward. */
 } fs_opts;
 
 enum { FS_SCHED_GRID = 0, FS_SCHED_PERSISTENT = 1, FS_SCHED_SPLIT = 2 };
+enum { FS_TOPK_FIRST = 0, FS_TOPK_WEIGHT = 1 };
 
 /* Per (view, surfel), fs_preprocess leaves FS_TILE_CACHE_WORDS uint32 for
    fs_bin: the depth key and, for footprints of at most FS_INLINE_TILES tiles,

@@ -16,6 +16,7 @@ FS_OK, FS_ERR_ARG, FS_ERR_CAPACITY, FS_ERR_HIP, FS_ERR_UNSUPPORTED = 0, 1, 2, 3,
 FS_TILES_PRECISE, FS_TILES_BBOX = 0, 1
 FS_FEAT_F32, FS_FEAT_BF16 = 0, 1
 FS_SCHED_GRID, FS_SCHED_PERSISTENT, FS_SCHED_SPLIT = 0, 1, 2
+FS_TOPK_FIRST, FS_TOPK_WEIGHT = 0, 1
 FS_RECORD_BYTES = 96
 FS_TILE_CACHE_WORDS = 4
 FS_GRAD_RECORD_FLOATS = 12
@@ -31,11 +32,12 @@ class FsCamera(ctypes.Structure):
 class FsOpts(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("topk", ctypes.c_int32), ("tile_mode", ctypes.c_int32),
                 ("feat_dtype", ctypes.c_int32), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
-                ("t_stop", ctypes.c_float), ("batch", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+                ("t_stop", ctypes.c_float), ("batch", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("topk_mode", ctypes.c_int32)]
 
 
 assert ctypes.sizeof(FsCamera) == 88
-assert ctypes.sizeof(FsOpts) == 36
+assert ctypes.sizeof(FsOpts) == 40
 
 
 class FastSegSimError(RuntimeError):
@@ -97,8 +99,8 @@ def check(status: int, what: str) -> None:
 
 def make_opts(tile: int = 16, topk: int = 0, tile_mode: int = FS_TILES_PRECISE, feat_dtype: int = FS_FEAT_F32,
               alpha_min: float = 1.0 / 255.0, alpha_max: float = 0.99, t_stop: float = 1e-4,
-              batch: int = 0, schedule: int = FS_SCHED_GRID) -> FsOpts:
-    return FsOpts(tile, topk, tile_mode, feat_dtype, alpha_min, alpha_max, t_stop, batch, schedule)
+              batch: int = 0, schedule: int = FS_SCHED_GRID, topk_mode: int = FS_TOPK_FIRST) -> FsOpts:
+    return FsOpts(tile, topk, tile_mode, feat_dtype, alpha_min, alpha_max, t_stop, batch, schedule, topk_mode)
 
 
 def make_cameras(cams, tile: int):

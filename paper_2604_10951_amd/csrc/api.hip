@@ -28,7 +28,15 @@ bool valid_opts(const fs_opts* o) {
     if (o->schedule != FS_SCHED_GRID && o->schedule != FS_SCHED_PERSISTENT && o->schedule != FS_SCHED_SPLIT)
         return false;
     if (o->schedule == FS_SCHED_SPLIT && o->topk < 1) return false;
+    if (o->topk_mode != FS_TOPK_FIRST && o->topk_mode != FS_TOPK_WEIGHT) return false;
+    if (o->topk_mode == FS_TOPK_WEIGHT && o->topk < 1) return false;
     return true;
+}
+
+// Valid options this build cannot run: Top-K by weight outside the split
+// schedule or beyond the compact lists.
+bool unsupported_opts(const fs_opts* o) {
+    return o->topk_mode == FS_TOPK_WEIGHT && (o->schedule != FS_SCHED_SPLIT || o->topk > FS_TOPK_COMPACT_K);
 }
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
@@ -180,7 +188,7 @@ fs_status fs_render_forward(const void* records, const uint32_t* vals, const uin
     if (!valid_opts(opts) || C < 1 || n < 1 || num_views < 1 || total_tiles < 1 || !cams_dev) return FS_ERR_ARG;
     if (!records || !tile_ranges || !feats || !out_feat || !out_T || !out_n) return FS_ERR_ARG;
     if (out_idx && opts->topk < 1) return FS_ERR_ARG;
-    if (C > 1024) return FS_ERR_UNSUPPORTED;
+    if (C > 1024 || unsupported_opts(opts)) return FS_ERR_UNSUPPORTED;
     FsWorkspace ws;
     memset(&ws, 0, sizeof(ws));
     if (opts->schedule != FS_SCHED_GRID) {
@@ -209,6 +217,7 @@ fs_status fs_render_backward(const float* means, const float* scales, const floa
         !grad_feats)
         return FS_ERR_ARG;
     if (C > 128) return FS_ERR_UNSUPPORTED;   // one channel chunk per block in the backward
+    if (opts->topk_mode == FS_TOPK_WEIGHT) return FS_ERR_UNSUPPORTED;   // no backward of the by-weight selection
     FsWorkspace ws;
     memset(&ws, 0, sizeof(ws));
     if (opts->topk > 0) {

@@ -549,6 +549,47 @@ FS_DEV int64_t block_row_chunk(const fs_camera* cams, int S) {
     return tiles_x * sb * sb;
 }
 
+// Bitonic sort of 64 << LOGE keys by one wave, in registers: element
+// i = lane * 2^LOGE + e is x[e] of its lane.  Compare-exchange partners
+// i ^ j with j < 2^LOGE sit in the same lane; with larger j they are the
+// same register of lane ^ (j >> LOGE), fetched by a shuffle.  The network is
+// the textbook one (stage k, distance j, ascending where i & k == 0).
+template <int LOGE>
+FS_DEV void wave_network(uint64_t (&x)[1 << LOGE]) {
+    constexpr int E = 1 << LOGE;
+    constexpr int LOGN = 6 + LOGE;
+    const int lane = (int)threadIdx.x & 63;
+#pragma unroll
+    for (int lk = 1; lk <= LOGN; ++lk) {
+        const int k = 1 << lk;
+#pragma unroll
+        for (int lj = lk - 1; lj >= 0; --lj) {
+            const int j = 1 << lj;
+            if (lj >= LOGE) {
+                const int lm = j >> LOGE;   // lane distance
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int i = lane * E + e;
+                    const uint64_t y = __shfl_xor(x[e], lm, 64);
+                    const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
+                    const bool lt = y < x[e];
+                    x[e] = (keep_min == lt) ? y : x[e];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    if ((e & j) != 0) continue;
+                    const int i = lane * E + e;
+                    const uint64_t a = x[e], b = x[e | j];
+                    const bool swap = (b < a) == ((i & k) == 0);
+                    x[e] = swap ? b : a;
+                    x[e | j] = swap ? a : b;
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launch helpers implemented in the .hip files.
 // ---------------------------------------------------------------------------

@@ -36,7 +36,7 @@ static_assert(kStagedK <= kCompactK, "the staged gather reads compact lists");
 
 // KC > 0: every pixel's list (at most KC pairs) is kept in LDS during the
 // walk and written compactly at the end; KC = 0: lists written in place.
-template <int KC>
+template <int KC, bool BYW>
 struct SelShared {
     FsRecord rec[kSelBatch];
     uint32_t recid[kSelBatch];
@@ -45,13 +45,19 @@ struct SelShared {
     uint64_t pixels[kSelBatch];    // per entry: pixels of the block inside its box that are still walking
     uint32_t mask[64];             // per pixel: entries of the batch it accepts
     uint2 list[64 * (KC > 0 ? KC : 1)];   // per pixel: (batch entry, then row slot; weight)
+    uint32_t uniq[BYW ? 64 * KC : 1];     // by weight: the block's distinct selected records
 };
 
 // List layout in the workspace, per 8x8 block b (region b * 64 * K of the
 // pair array): with KC > 0 the pairs of pixel p start at the sum of the
 // counts of pixels 0 .. p - 1 (compact), and nrows[b] = rows | pairs << 16;
 // with KC = 0 they start at p * K and nrows[b] = rows.
-template <int KC>
+// BYW (Top-K by weight, KC > 0): no pixel stops at K; each keeps, in its LDS
+// list and in depth order, the K blended entries of largest weight seen so
+// far (list position, weight).  After the walk the block's distinct selected
+// list positions are sorted and numbered: they are its row list, in list
+// order as in the first-K mode, and every pair's position becomes its slot.
+template <int KC, bool BYW>
 __global__ void __launch_bounds__(64)
 topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restrict__ vals,
                    const uint32_t* __restrict__ ranges, uint32_t n, int64_t num_records,
@@ -62,7 +68,8 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
     constexpr int BG = kSelBatch;
     constexpr int kQ = FS_RECORD_BYTES / 16;          // float4 per record
     constexpr int kRecSlots = (BG * kQ + 63) / 64;    // record float4 per lane
-    __shared__ SelShared<KC> sm;
+    static_assert(!BYW || KC > 0, "the by-weight lists live in LDS");
+    __shared__ SelShared<KC, BYW> sm;
     const int lane = threadIdx.x;
     const int64_t block = xcd_remap_chunked(blockIdx.x, nblocks, block_row_chunk(cams, S));
     const BlockPos bp = locate_block(block, S, 8, cams, num_views);
@@ -225,6 +232,31 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
             const double Tn = T * (1.0 - (double)al);
             if (Tn < t_stop) {
                 done = true;
+            } else if constexpr (BYW) {
+                // the entry a full list drops: the lightest, the back one on
+                // ties; a new entry enters only if strictly heavier
+                const float w = (float)((double)al * T);
+                uint2* __restrict__ lst = &sm.list[lane * KC];
+                if (cnt < K) {
+                    lst[cnt] = make_uint2(b0 + (uint32_t)e, __float_as_uint(w));
+                    ++cnt;
+                } else {
+                    int m = 0;
+                    float wm = __uint_as_float(lst[0].y);
+                    for (int j = 1; j < K; ++j) {
+                        const float wj = __uint_as_float(lst[j].y);
+                        if (wj <= wm) {
+                            wm = wj;
+                            m = j;
+                        }
+                    }
+                    if (w > wm) {
+                        for (int j = m; j < K - 1; ++j) lst[j] = lst[j + 1];
+                        lst[K - 1] = make_uint2(b0 + (uint32_t)e, __float_as_uint(w));
+                    }
+                }
+                T = Tn;
+                last = (int)(b0 + e);
             } else {
                 bm |= 1u << e;
                 if constexpr (KC > 0) {
@@ -236,6 +268,10 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
                 last = (int)(b0 + e);
                 if (cnt == K) done = true;
             }
+        }
+        if constexpr (BYW) {
+            if (__all(done)) break;
+            continue;   // rows are numbered after the walk
         }
         // (c) row slots: the entries any pixel of the block blends get
         //     consecutive slots of the block's row list, in list order
@@ -271,6 +307,60 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
         if (__all(done)) break;
     }
 
+    if constexpr (BYW) {
+        constexpr int LOGE = KC == 8 ? 3 : 4;
+        static_assert(KC == (1 << LOGE), "one register per list slot");
+        uint2* __restrict__ lst = &sm.list[lane * KC];
+        // the block's distinct selected list positions, sorted (a record
+        // holds one position of the tile's list, and numbering rows by
+        // position keeps every pixel's slots increasing, as the gather's
+        // row windows need): element lane * KC + j is x[j]
+        uint64_t x[KC];
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+            x[j] = ~0ull;
+            if (j < cnt) {
+                x[j] = lst[j].x;
+                if (out_idx) out_idx[pix * K + j] = (int32_t)vals[lst[j].x];
+            }
+        }
+        wave_network<LOGE>(x);
+        const uint64_t before = __shfl_up(x[KC - 1], 1, 64);
+        uint32_t heads = 0u;
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+            const uint64_t prev = j > 0 ? x[j - 1] : (lane > 0 ? before : ~0ull);
+            if (x[j] != ~0ull && x[j] != prev) heads |= 1u << j;
+        }
+        const int nh = __popc(heads);
+        int incl = nh;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += y;
+        }
+        const uint32_t R = (uint32_t)__shfl(incl, 63, 64);
+        int rank = incl - nh;
+#pragma unroll
+        for (int j = 0; j < KC; ++j)
+            if ((heads >> j) & 1u) sm.uniq[rank++] = (uint32_t)x[j];
+        __syncthreads();
+        // every pair's row slot: the rank of its position
+        for (int j = 0; j < cnt; ++j) {
+            const uint32_t pos = lst[j].x;
+            uint32_t lo = 0u, hi = R;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (sm.uniq[mid] < pos)
+                    lo = mid + 1u;
+                else
+                    hi = mid;
+            }
+            lst[j].x = lo;
+        }
+        for (uint32_t t = (uint32_t)lane; t < R; t += 64u) rowlist[t] = vals[sm.uniq[t]] % n;
+        nslots = R;
+    }
     if (counters != nullptr) {
         int c = cnt;
 #pragma unroll
@@ -602,8 +692,11 @@ hipError_t fs_launch_topk_select(const FsRecord* records, const uint32_t* vals, 
     if (ws.topk_pairs == nullptr || ws.topk_rows == nullptr || ws.topk_nrows == nullptr ||
         ws.topk_pair_slots < nblocks * 64 * (int64_t)o.topk || nblocks >= (int64_t(1) << 31))
         return hipErrorInvalidValue;
-    auto kern = o.topk <= 8 ? topk_select_kernel<8> : (o.topk <= kCompactK ? topk_select_kernel<kCompactK>
-                                                                           : topk_select_kernel<0>);
+    auto kern = o.topk_mode == FS_TOPK_WEIGHT
+                    ? (o.topk <= 8 ? topk_select_kernel<8, true> : topk_select_kernel<kCompactK, true>)
+                    : (o.topk <= 8 ? topk_select_kernel<8, false>
+                                   : (o.topk <= kCompactK ? topk_select_kernel<kCompactK, false>
+                                                          : topk_select_kernel<0, false>));
     hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(64), 0, s, records, vals, ranges, (uint32_t)n,
                        n * num_views, cams, num_views, o.tile, o, nblocks, ws.topk_pairs, ws.topk_rows,
                        ws.topk_nrows, out_T, out_n, out_last, out_idx, counters);

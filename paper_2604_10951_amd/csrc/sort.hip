@@ -287,42 +287,6 @@ FS_DEV void sort_run_lds(uint64_t* s, const uint2* __restrict__ in, uint64_t til
 // fetched by a shuffle.  The network is the textbook one (stage k, distance
 // j, ascending where i & k == 0), so the result is the sorted run.
 template <int LOGE>
-FS_DEV void wave_network(uint64_t (&x)[1 << LOGE]) {
-    constexpr int E = 1 << LOGE;
-    constexpr int LOGN = 6 + LOGE;
-    const int lane = (int)threadIdx.x & 63;
-#pragma unroll
-    for (int lk = 1; lk <= LOGN; ++lk) {
-        const int k = 1 << lk;
-#pragma unroll
-        for (int lj = lk - 1; lj >= 0; --lj) {
-            const int j = 1 << lj;
-            if (lj >= LOGE) {
-                const int lm = j >> LOGE;   // lane distance
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const int i = lane * E + e;
-                    const uint64_t y = __shfl_xor(x[e], lm, 64);
-                    const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
-                    const bool lt = y < x[e];
-                    x[e] = (keep_min == lt) ? y : x[e];
-                }
-            } else {
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    if ((e & j) != 0) continue;
-                    const int i = lane * E + e;
-                    const uint64_t a = x[e], b = x[e | j];
-                    const bool swap = (b < a) == ((i & k) == 0);
-                    x[e] = swap ? b : a;
-                    x[e | j] = swap ? a : b;
-                }
-            }
-        }
-    }
-}
-
-template <int LOGE>
 FS_DEV void sort_run_wave(const uint2* __restrict__ in, uint64_t tile, uint32_t start, int n,
                           uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     constexpr int E = 1 << LOGE;

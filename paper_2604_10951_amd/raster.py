@@ -66,7 +66,7 @@ class Rasterizer:
 
     def __init__(self, cams, *, tile: int = 16, topk: int = 0, tile_mode: str = "precise",
                  feat_dtype: str = "f32", alpha_min: float = ALPHA_MIN, alpha_max: float = ALPHA_MAX,
-                 t_stop: float = T_STOP, batch: int = 0, schedule: str = "auto",
+                 t_stop: float = T_STOP, batch: int = 0, schedule: str = "auto", topk_mode: str = "first",
                  device: str | torch.device = "cuda", pair_capacity: int = 0):
         self.lib = L.load()
         self.device = torch.device(device)
@@ -78,7 +78,8 @@ class Rasterizer:
         if schedule == "auto":   # the measured fastest: split for Top-K, the fused grid for the full blend
             schedule = "split" if topk > 0 else "grid"
         sched = {"grid": L.FS_SCHED_GRID, "persistent": L.FS_SCHED_PERSISTENT, "split": L.FS_SCHED_SPLIT}[schedule]
-        self.opts = L.make_opts(tile, topk, mode, dt, alpha_min, alpha_max, t_stop, batch, sched)
+        kmode = {"first": L.FS_TOPK_FIRST, "weight": L.FS_TOPK_WEIGHT}[topk_mode]
+        self.opts = L.make_opts(tile, topk, mode, dt, alpha_min, alpha_max, t_stop, batch, sched, kmode)
         self.cam_arr, self.total_tiles, self.total_pixels = L.make_cameras(self.cams, tile)
         raw = bytes(ctypes.string_at(ctypes.addressof(self.cam_arr), ctypes.sizeof(self.cam_arr)))
         self.cams_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)

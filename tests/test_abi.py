@@ -58,6 +58,16 @@ def test_host_only_entry_points_without_gpu():
     o5 = _lib.make_opts(topk=8, schedule=_lib.FS_SCHED_SPLIT)
     assert lib.fs_preprocess(None, None, None, None, 0, ctypes.c_void_p(1), 1, ctypes.byref(o5), None, None,
                              None, None) == _lib.FS_OK
+    # Top-K modes: an unknown mode and a by-weight full blend are invalid
+    o6 = _lib.make_opts(topk=8, schedule=_lib.FS_SCHED_SPLIT, topk_mode=2)
+    assert lib.fs_preprocess(None, None, None, None, 0, ctypes.c_void_p(1), 1, ctypes.byref(o6), None, None,
+                             None, None) == _lib.FS_ERR_ARG
+    o7 = _lib.make_opts(topk=0, topk_mode=_lib.FS_TOPK_WEIGHT)
+    assert lib.fs_preprocess(None, None, None, None, 0, ctypes.c_void_p(1), 1, ctypes.byref(o7), None, None,
+                             None, None) == _lib.FS_ERR_ARG
+    o8 = _lib.make_opts(topk=8, schedule=_lib.FS_SCHED_SPLIT, topk_mode=_lib.FS_TOPK_WEIGHT)
+    assert lib.fs_preprocess(None, None, None, None, 0, ctypes.c_void_p(1), 1, ctypes.byref(o8), None, None,
+                             None, None) == _lib.FS_OK
     # the tile cache must be 16-byte aligned
     assert lib.fs_preprocess(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 1,
                              ctypes.c_void_p(16), 1, ctypes.byref(o5), ctypes.c_void_p(16), ctypes.c_void_p(16),
