@@ -113,6 +113,28 @@ def form_bf16(dev, steps, warmup):
     return res
 
 
+def form_topk_weight(dev, steps, warmup):
+    """Top-K by weight (the K largest alpha T of each pixel's walk) against the
+    first-K reading on the 300k-surfel, 640x480, C = 64 workload, K in
+    {4, 8, 16}, split schedule: frame time and the relative L2 distance of the
+    feature image from the full blend."""
+    scene, cam = scenes.topk_scene()
+    tens = raster.scene_tensors(scene, dev)
+    res = {"workload": "300k surfels, 640x480, C=64, 8x8 tiles, split schedule, K in {4, 8, 16}",
+           "full_blend_ms": _plain(cam, tens, dev, steps, warmup)}
+    full = raster.Rasterizer(cam, tile=8, topk=0, device=dev).render(*tens).feat
+    norm = float(full.norm())
+    for K in (4, 8, 16):
+        for mode in ("first", "weight"):
+            rast = raster.Rasterizer(cam, tile=8, topk=K, topk_mode=mode, schedule="split", device=dev)
+            fr = rast.render(*tens)
+            res[f"K{K}_{mode}_rel_l2_vs_full"] = float((fr.feat - full).norm()) / norm
+            res[f"K{K}_{mode}_ms"] = _time_frames(rast, tens, steps, warmup)
+            del rast, fr
+            torch.cuda.empty_cache()
+    return res
+
+
 def form_batched(scene_tens, dev, steps, warmup):
     """1M surfels, 16 look-at views of uneven resolution, C = 128, K = 8: one
     hipGraph replay of the batched frame (split Top-K render: measured 4.1 ms
@@ -241,7 +263,7 @@ def main():
     ap.add_argument("--schedule", default="split", choices=("grid", "persistent", "split"),
                     help="render schedule of the Top-K frames (the full blend uses 'grid')")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 / batched / backward forms")
-    ap.add_argument("--form", choices=("batched", "backward", "bf16"), default=None,
+    ap.add_argument("--form", choices=("batched", "backward", "bf16", "topk_weight"), default=None,
                     help="run only this form and print its JSON line (profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer 3 times (reference for HBM byte counters)")
@@ -257,6 +279,8 @@ def main():
             res = form_backward(dev, fs, fw)
         elif args.form == "bf16":
             res = form_bf16(dev, fs, fw)
+        elif args.form == "topk_weight":
+            res = form_topk_weight(dev, fs, fw)
         else:
             scene, _ = scenes.headline(seed=args.seed, channels=C)
             res = form_batched(raster.scene_tensors(scene, dev), dev, fs, fw)
@@ -335,6 +359,8 @@ def main():
         forms["backward"] = form_backward(dev, fs, fw)
         print("[bench] form: bf16", file=sys.stderr, flush=True)
         forms["bf16"] = form_bf16(dev, fs, fw)
+        print("[bench] form: Top-K by weight", file=sys.stderr, flush=True)
+        forms["topk_weight"] = form_topk_weight(dev, fs, fw)
         line["forms"] = forms
     if not args.no_cpu:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
