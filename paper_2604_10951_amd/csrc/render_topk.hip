@@ -3,19 +3,20 @@
 // Selection (lanes = pixels, one wave per 8x8 block): walks the block's
 // depth-sorted tile list front to back with exactly the per-pixel arithmetic
 // of the fused renderer (ray-splat response, alpha, transmittance, the T_stop
-// and K tests) and writes, for every pixel, the surfel index and blend weight
-// w = alpha T of each of its first K blended surfels to the workspace, plus
-// the final transmittance, blend count and optional index outputs.  It holds
-// no feature data, so it runs at high occupancy and hides the latency of its
-// dependent list -> record loads behind other waves.
+// and K tests) and writes, for every pixel, the row slot and blend weight
+// w = alpha T of each of its first K blended surfels (or, by weight, of the K
+// heaviest of its walk) to the workspace, the block's row list (slot ->
+// surfel), plus the final transmittance, blend count and optional index
+// outputs.  It holds no feature data, so it runs at high occupancy and hides
+// the latency of its dependent list -> record loads behind other waves.
 //
-// Gather (lanes = (pixel, 16-byte channel vector)): every thread reads its
-// pixel's (surfel, weight) list, issues the loads of all listed feature rows
-// before the first multiply-add, and accumulates w * c in list order with the
-// same fused multiply-adds as the fused renderer, so both schedules give the
-// same bits.  This pass is a stream: the feature image written (pixel-major,
-// C floats per pixel) dominates its traffic, and the rows it reads are shared
-// by neighbouring pixels and served mostly by L2.
+// Gather (one workgroup per block, lanes = (pixel, 16-byte channel vector)):
+// stages the block's lists and its rows in LDS, then every thread
+// accumulates w * c over its pixel's list in list order with the same fused
+// multiply-adds as the fused renderer, so both schedules give the same bits.
+// This pass is a stream: the feature image written (pixel-major, C floats per
+// pixel) dominates its traffic, and the rows it reads are shared by
+// neighbouring blocks and served mostly by L2.
 //
 // Both launches hand the XCDs one tile row of blocks each in turn
 // (neighbouring tiles share surfels, so their records and rows stay in that
