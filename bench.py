@@ -135,6 +135,30 @@ def form_topk_weight(dev, steps, warmup):
     return res
 
 
+def form_labels(scene_tens, dev, steps, warmup):
+    """Segmentation labels (per-pixel argmax channel and its score) of the
+    1M-surfel, 1280x720, C = 128, K = 8 frame: the split render with the label
+    epilogue against the same frame writing its feature image."""
+    cam = scenes.centred_camera(1280, 720)
+    rast = raster.Rasterizer(cam, tile=8, topk=8, schedule="split", device=dev)
+    fr = rast.render(*scene_tens)
+    res = {"workload": "1M surfels, 1280x720, C=128, Top-K K=8, 8x8 tiles, split schedule"}
+    feat_ms, feat_st = time_pipeline(rast, scene_tens, rast.alloc_out(C), steps, warmup)
+    lab = rast.alloc_labels()
+    cnt = render_counters(rast, scene_tens, lab)
+    lab_ms, lab_st = time_pipeline(rast, scene_tens, lab, steps, warmup)
+    H, W = cam.height, cam.width
+    nbytes = fr.num_pairs * (4 + 96) + cnt["rows"] * C * 4 + H * W * 16   # label, score, T, n per pixel
+    res.update({"features_frame_ms": feat_ms, "features_render_ms": feat_st["render"],
+                "labels_frame_ms": lab_ms, "labels_render_ms": lab_st["render"],
+                "labels_fps": 1e3 / lab_ms, "labels_vs_features_frame": feat_ms / lab_ms,
+                "labels_render_algorithmic_bytes": nbytes,
+                "labels_render_hbm_frac": nbytes / (lab_st["render"] * 1e-3) / 1e9 / HBM_PEAK_GBS})
+    del rast, fr, lab
+    torch.cuda.empty_cache()
+    return res
+
+
 def form_batched(scene_tens, dev, steps, warmup):
     """1M surfels, 16 look-at views of uneven resolution, C = 128, K = 8: one
     hipGraph replay of the batched frame (split Top-K render: measured 4.1 ms
@@ -263,7 +287,7 @@ def main():
     ap.add_argument("--schedule", default="split", choices=("grid", "persistent", "split"),
                     help="render schedule of the Top-K frames (the full blend uses 'grid')")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 / batched / backward forms")
-    ap.add_argument("--form", choices=("batched", "backward", "bf16", "topk_weight"), default=None,
+    ap.add_argument("--form", choices=("batched", "backward", "bf16", "topk_weight", "labels"), default=None,
                     help="run only this form and print its JSON line (profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer 3 times (reference for HBM byte counters)")
@@ -281,6 +305,9 @@ def main():
             res = form_bf16(dev, fs, fw)
         elif args.form == "topk_weight":
             res = form_topk_weight(dev, fs, fw)
+        elif args.form == "labels":
+            scene, _ = scenes.headline(seed=args.seed, channels=C)
+            res = form_labels(raster.scene_tensors(scene, dev), dev, fs, fw)
         else:
             scene, _ = scenes.headline(seed=args.seed, channels=C)
             res = form_batched(raster.scene_tensors(scene, dev), dev, fs, fw)
@@ -353,6 +380,8 @@ def main():
         fs, fw = 10, 2
         print("[bench] form: batched views", file=sys.stderr, flush=True)
         forms = {"batched": form_batched(tens, dev, fs, fw)}
+        print("[bench] form: labels", file=sys.stderr, flush=True)
+        forms["labels"] = form_labels(tens, dev, fs, fw)
         del tens
         torch.cuda.empty_cache()
         print("[bench] form: backward", file=sys.stderr, flush=True)

@@ -16,6 +16,8 @@
  *   fs_render_forward   per-pixel front-to-back blending of C-channel features,
  *                       full (Sec. 3.1 Eq. 2) or Top-K hard selection
  *                       (Sec. 3.4, F_TopK)
+ *   fs_render_labels    the same render reduced per pixel to the argmax channel
+ *                       and its value (segmentation masks, Sec. 3.3, 3.5)
  *   fs_render_backward  gradients of a loss on the rendered features w.r.t.
  *                       surfel centres, scales, rotations, opacities and
  *                       features (the renderer is trained end to end, Sec. 3.5)
@@ -227,6 +229,26 @@ fs_status fs_render_forward(const void* records, const uint32_t* vals, const uin
                             int32_t C, int64_t n, const fs_camera* cams_dev, int32_t num_views, int64_t total_tiles,
                             const fs_opts* opts, float* out_feat, float* out_T, int32_t* out_n, int32_t* out_last,
                             int32_t* out_idx, uint64_t* counters, void* workspace, hipStream_t stream);
+
+/*
+ * fs_render_labels (Sec. 3.3, Sec. 3.5: segmentation masks come from
+ * blending per-Gaussian class or instance scores as channels; a pixel's label
+ * is read here as its best-scoring channel).  The
+ * Top-K render of fs_render_forward with the split schedule (opts->schedule
+ * = FS_SCHED_SPLIT, topk >= 1, either topk_mode), where each pixel's
+ * blended vector F (the same float32 values fs_render_forward writes) is
+ * reduced to
+ *   out_label  out, total_pixels int32: argmax_c F[c], the lowest c among
+ *              equal maxima (0 for a pixel that blends nothing)
+ *   out_score  optional out, total_pixels float32: F[out_label]
+ * instead of being stored; the C floats per pixel never reach memory.
+ * out_T, out_n, counters, workspace and the other arguments as in
+ * fs_render_forward.  FS_ERR_UNSUPPORTED for another schedule or C > 1024.
+ */
+fs_status fs_render_labels(const void* records, const uint32_t* vals, const uint32_t* tile_ranges, const void* feats,
+                           int32_t C, int64_t n, const fs_camera* cams_dev, int32_t num_views, int64_t total_tiles,
+                           const fs_opts* opts, int32_t* out_label, float* out_score, float* out_T, int32_t* out_n,
+                           uint64_t* counters, void* workspace, hipStream_t stream);
 
 /*
  * fs_render_backward.  Given dL/dF (grad_feat, total_pixels x C float32) for

@@ -15,6 +15,8 @@ Functions and the paper passage each follows:
   sort_pairs     (tile, depth) ordering                        Sec. 3.1 (depth-sorted surfels)
   render_image / render_pixels
                  front-to-back blend, full or Top-K            Sec. 3.1 Eq. (2), Sec. 3.4 F_TopK
+  labels         per-pixel argmax channel of a render          Sec. 3.3, Sec. 3.5 (masks from blended
+                                                               class / instance channels)
   render_grad    chain rule of the blend (held decisions)     training through the renderer, Sec. 3.5
   finite_difference  central differences of render_image      (pins render_grad)
 
@@ -275,6 +277,25 @@ def render_scene(scene, cam, *, K: int = 0, kcap: int | None = None, alpha_min: 
     return render_image(proj, scene.opacity, scene.feats if feats is None else feats, cam.width, cam.height, K=K,
                         kcap=kcap, alpha_min=alpha_min, alpha_max=alpha_max, t_stop=t_stop, prefilter=prefilter,
                         by_weight=by_weight)
+
+
+def labels(r: Render, rel_tol: float = 0.0):
+    """Segmentation label of every pixel of a render (Sec. 3.3, Sec. 3.5: the
+    masks come from blending per-Gaussian class or instance scores as
+    channels; the label is read as the best-scoring channel).
+
+    Returns (label, score, near): label = the channel of largest F, the lowest
+    one among equal maxima (0 for a pixel with no contributor); score = F at
+    that channel; near = (..., C) mask of the channels that could still be
+    the largest if every F[c] were off by up to rel_tol * absF[c] (a render in
+    lower precision may pick any of them; near has one channel where the
+    choice is certain)."""
+    F, A = r.F, r.absF
+    label = np.argmax(F, axis=-1)
+    score = np.take_along_axis(F, label[..., None], axis=-1)[..., 0]
+    lo = score - rel_tol * np.take_along_axis(A, label[..., None], axis=-1)[..., 0]
+    near = F + rel_tol * A >= lo[..., None]
+    return label, score, near
 
 
 @dataclass

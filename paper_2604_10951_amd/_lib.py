@@ -64,6 +64,7 @@ SIGNATURES = {
     "fs_bin": ([P, P, P, P, I64, P, I32, ctypes.POINTER(FsOpts), P, P, P, P, I64, P, ctypes.POINTER(I64), P, P], I32),
     "fs_sort": ([P, P, I64, P, I64, I64, P, P, P], I32),
     "fs_render_forward": ([P, P, P, P, I32, I64, P, I32, I64, ctypes.POINTER(FsOpts), P, P, P, P, P, P, P, P], I32),
+    "fs_render_labels": ([P, P, P, P, I32, I64, P, I32, I64, ctypes.POINTER(FsOpts), P, P, P, P, P, P, P], I32),
     "fs_render_backward": ([P, P, P, P, P, P, P, P, I32, I64, P, I32, I64, ctypes.POINTER(FsOpts), P, P, P, P, P, P,
                             P, P, P, P, P, P], I32),
     "fs_status_string": ([I32], ctypes.c_char_p),

@@ -197,11 +197,27 @@ fs_status fs_render_forward(const void* records, const uint32_t* vals, const uin
     }
     if (opts->schedule == FS_SCHED_SPLIT)
         return hip_status(fs_launch_render_topk_split(static_cast<const FsRecord*>(records), vals, tile_ranges, feats,
-                                                      C, n, cams_dev, num_views, total_tiles, *opts, out_feat, out_T,
-                                                      out_n, out_last, out_idx, counters, ws, stream));
+                                                      C, n, cams_dev, num_views, total_tiles, *opts, out_feat,
+                                                      nullptr, nullptr, out_T, out_n, out_last, out_idx, counters, ws,
+                                                      stream));
     return hip_status(fs_launch_render_forward(static_cast<const FsRecord*>(records), vals, tile_ranges, feats, C, n,
                                                cams_dev, num_views, total_tiles, *opts, out_feat, out_T, out_n,
                                                out_last, out_idx, counters, ws, stream));
+}
+
+fs_status fs_render_labels(const void* records, const uint32_t* vals, const uint32_t* tile_ranges, const void* feats,
+                           int32_t C, int64_t n, const fs_camera* cams_dev, int32_t num_views, int64_t total_tiles,
+                           const fs_opts* opts, int32_t* out_label, float* out_score, float* out_T, int32_t* out_n,
+                           uint64_t* counters, void* workspace, hipStream_t stream) {
+    if (!valid_opts(opts) || C < 1 || n < 1 || num_views < 1 || total_tiles < 1 || !cams_dev) return FS_ERR_ARG;
+    if (!records || !tile_ranges || !feats || !out_label || !out_T || !out_n || !workspace) return FS_ERR_ARG;
+    if (C > 1024 || unsupported_opts(opts) || opts->schedule != FS_SCHED_SPLIT) return FS_ERR_UNSUPPORTED;
+    FsWorkspace ws;
+    memset(&ws, 0, sizeof(ws));
+    if (!fs_workspace_layout(workspace, 0, 1, total_tiles, 0, opts, &ws, nullptr)) return FS_ERR_ARG;
+    return hip_status(fs_launch_render_topk_split(static_cast<const FsRecord*>(records), vals, tile_ranges, feats, C,
+                                                  n, cams_dev, num_views, total_tiles, *opts, nullptr, out_label,
+                                                  out_score, out_T, out_n, nullptr, nullptr, counters, ws, stream));
 }
 
 fs_status fs_render_backward(const float* means, const float* scales, const float* quats, const float* opacity,

@@ -664,11 +664,13 @@ hipError_t fs_launch_topk_select(const FsRecord* records, const uint32_t* vals, 
                                  float* out_T, int32_t* out_n, int32_t* out_last, int32_t* out_idx,
                                  uint64_t* counters, const FsWorkspace& ws, hipStream_t s);
 
+// Both passes of the split Top-K renderer.  Exactly one of out_feat (feature
+// image) and out_label (per-pixel channel argmax, out_score optional) is set.
 hipError_t fs_launch_render_topk_split(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges,
                                        const void* feats, int C, int64_t n, const fs_camera* cams, int num_views,
-                                       int64_t total_tiles, const fs_opts& o, float* out_feat, float* out_T,
-                                       int32_t* out_n, int32_t* out_last, int32_t* out_idx, uint64_t* counters,
-                                       const FsWorkspace& ws, hipStream_t s);
+                                       int64_t total_tiles, const fs_opts& o, float* out_feat, int32_t* out_label,
+                                       float* out_score, float* out_T, int32_t* out_n, int32_t* out_last,
+                                       int32_t* out_idx, uint64_t* counters, const FsWorkspace& ws, hipStream_t s);
 
 hipError_t fs_launch_render_backward(const float* means, const float* scales, const float* quats,
                                      const float* opacity, const FsRecord* records, const uint32_t* vals,

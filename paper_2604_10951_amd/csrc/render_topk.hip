@@ -450,17 +450,54 @@ FS_DEV void store_vec(float* __restrict__ dst, int c0, const float* acc) {
     }
 }
 
+// Label epilogue: in place of its feature vector a pixel gets the channel
+// holding its largest blended value (equal values go to the lower channel)
+// and that value.  Each thread reduces its own channels, then the TPP lanes
+// of the pixel (consecutive lanes of one wave) exchange their candidates.
+FS_DEV void argmax_take(float x, int c, float& v, int& cv) {
+    if (x > v || (x == v && c < cv)) {
+        v = x;
+        cv = c;
+    }
+}
+template <int TPP>
+FS_DEV void argmax_lanes(float& v, int& c) {
+#pragma unroll
+    for (int d = 1; d < TPP; d <<= 1) argmax_take(__shfl_xor(v, d, 64), __shfl_xor(c, d, 64), v, c);
+}
+// Largest v over aligned groups of TPP lanes, every lane of the group
+// getting it: in-row DPP moves (quad swaps, then the mirrors within 8 and 16
+// lanes, each combining two halves already reduced) and one cross-row
+// exchange per further doubling.  Every lane of the wave must be active.
+template <int CTRL>
+FS_DEV float max_dpp(float v) {
+    return fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false)));
+}
+template <int TPP>
+FS_DEV float lanes_max(float v) {
+    v = max_dpp<0xb1>(v);                                  // quad_perm [1, 0, 3, 2]
+    v = max_dpp<0x4e>(v);                                  // quad_perm [2, 3, 0, 1]
+    if constexpr (TPP >= 8) v = max_dpp<0x141>(v);         // row_half_mirror
+    if constexpr (TPP >= 16) v = max_dpp<0x140>(v);        // row_mirror
+    if constexpr (TPP >= 32) v = fmaxf(v, __shfl_xor(v, 16, 64));
+    if constexpr (TPP >= 64) v = fmaxf(v, __shfl_xor(v, 32, 64));
+    return v;
+}
+constexpr float kNoValue = -__builtin_huge_valf();
+constexpr int kNoChannel = 0x7fffffff;
+
 // Gather, general form: TPP threads per pixel (a power of two, 4..64), each
 // taking channel vectors q, q + TPP, ... of its pixel and reading the pixel's
 // (slot, weight) list and the block's row list from memory.  A workgroup
 // covers 256 / TPP pixels of one 8x8 block.  Used when a pixel has more
 // channels or list slots than the staged form holds.
-template <typename FT, int VE, int TPP>
+template <typename FT, int VE, int TPP, bool LABEL>
 __global__ void __launch_bounds__(kGatherThreads)
 topk_gather_general_kernel(const uint2* __restrict__ pairs, const int32_t* __restrict__ counts,
                            const uint32_t* __restrict__ rows, const FT* __restrict__ feats, int C, int K,
                            const fs_camera* __restrict__ cams, int num_views, int S, int64_t ngroups,
-                           float* __restrict__ out_feat) {
+                           float* __restrict__ out_feat, int32_t* __restrict__ out_label,
+                           float* __restrict__ out_score) {
     using V = Vec<FT, VE>;
     constexpr int kPix = kGatherThreads / TPP;   // pixels per workgroup
     constexpr int kGroups = 64 / kPix;           // workgroups per block
@@ -497,7 +534,9 @@ topk_gather_general_kernel(const uint2* __restrict__ pairs, const int32_t* __res
     const uint2* __restrict__ mine = pairs + block * 64 * (int64_t)K + (compact ? s_off[p] : p * K);
     const uint32_t* __restrict__ rowlist = rows + block * 64 * (int64_t)K;
     const int nv = (C + VE - 1) / VE;
-    float* __restrict__ dst = out_feat + pix * C;
+    float* __restrict__ dst = LABEL ? nullptr : out_feat + pix * C;
+    float best = kNoValue;
+    int best_c = kNoChannel;
     for (int q = q0; q < nv; q += TPP) {
         const int c0 = q * VE;
         float acc[VE];
@@ -525,7 +564,19 @@ topk_gather_general_kernel(const uint2* __restrict__ pairs, const int32_t* __res
                 }
             }
         }
-        store_vec<VE>(dst, c0, acc);
+        if constexpr (LABEL) {
+#pragma unroll
+            for (int i = 0; i < VE; ++i) argmax_take(acc[i], c0 + i, best, best_c);
+        } else {
+            store_vec<VE>(dst, c0, acc);
+        }
+    }
+    if constexpr (LABEL) {
+        argmax_lanes<TPP>(best, best_c);
+        if (q0 == 0) {
+            out_label[pix] = best_c;
+            if (out_score) out_score[pix] = best;
+        }
     }
 }
 
@@ -535,12 +586,13 @@ topk_gather_general_kernel(const uint2* __restrict__ pairs, const int32_t* __res
 // in flight together), and every pixel adds the rows of its list that fall
 // in the window, front to back.  TPP threads per pixel, each owning one
 // 16-byte channel vector of kPasses pixels of the block.
-template <typename FT, int TPP, int W, int KC>
+template <typename FT, int TPP, int W, int KC, bool LABEL>
 __global__ void __launch_bounds__(kGatherThreads)
 topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restrict__ counts,
                        const uint32_t* __restrict__ rows, const uint32_t* __restrict__ nrows,
                        const FT* __restrict__ feats, int C, int K, const fs_camera* __restrict__ cams, int num_views,
-                       int S, int64_t nblocks, float* __restrict__ out_feat) {
+                       int S, int64_t nblocks, float* __restrict__ out_feat, int32_t* __restrict__ out_label,
+                       float* __restrict__ out_score) {
     constexpr int VE = 16 / (int)sizeof(FT);
     using V = Vec<FT, VE>;
     constexpr int kPix = kGatherThreads / TPP;   // pixels per pass
@@ -631,15 +683,37 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
     for (int k = 0; k < kPasses; ++k) {
         const int p = k * kPix + sub;
         const int px = bp.x0 + (p & 7), py = bp.y0 + (p >> 3);
-        if (px < cam.width && py < cam.height && has_vec)
-            store_vec<VE>(out_feat + (cam.pixel_offset + (int64_t)py * cam.width + px) * C, q * VE, acc[k]);
+        const bool on = px < cam.width && py < cam.height;
+        if constexpr (LABEL) {
+            // lane q holds channels q VE .. q VE + VE - 1, so lane order is
+            // channel order: the label is the own best of the lowest lane of
+            // the pixel whose best equals the pixel's maximum
+            float best = kNoValue;
+            int best_c = kNoChannel;
+            if (has_vec)
+#pragma unroll
+                for (int i = 0; i < VE; ++i) argmax_take(acc[k][i], q * VE + i, best, best_c);
+            const float m = lanes_max<TPP>(best);   // every lane of the workgroup is here
+            const int base = (tid & 63) & ~(TPP - 1);
+            const uint64_t seg = TPP == 64 ? ~0ull : ((1ull << TPP) - 1);
+            const uint64_t hit = (__ballot(best == m) >> base) & seg;   // m is some lane's best (finite sums)
+            const int label = __shfl(best_c, base + (hit ? __builtin_ctzll(hit) : 0), 64);
+            if (on && q == 0) {
+                const int64_t pix = cam.pixel_offset + (int64_t)py * cam.width + px;
+                out_label[pix] = label;
+                if (out_score) out_score[pix] = m;
+            }
+        } else {
+            if (on && has_vec)
+                store_vec<VE>(out_feat + (cam.pixel_offset + (int64_t)py * cam.width + px) * C, q * VE, acc[k]);
+        }
     }
 }
 
-template <typename FT, int VE>
+template <typename FT, int VE, bool LABEL>
 hipError_t launch_gather(const uint2* pairs, const int32_t* counts, const uint32_t* rows, const uint32_t* nrows,
                          const void* feats, int C, int K, const fs_camera* cams, int num_views, int S,
-                         int64_t nblocks, float* out_feat, hipStream_t s) {
+                         int64_t nblocks, float* out_feat, int32_t* out_label, float* out_score, hipStream_t s) {
     const int nv = (C + VE - 1) / VE;
     const FT* f = static_cast<const FT*>(feats);
     int tpp = 4;
@@ -648,12 +722,13 @@ hipError_t launch_gather(const uint2* pairs, const int32_t* counts, const uint32
         if (nblocks >= (int64_t(1) << 32)) return hipErrorInvalidValue;
 #define FS_GATHER_LDS(TPP, W)                                                                                     \
     if (K <= 8)                                                                                                    \
-        hipLaunchKernelGGL((topk_gather_lds_kernel<FT, TPP, W, 8>), dim3((unsigned)nblocks), dim3(kGatherThreads), \
-                           0, s, pairs, counts, rows, nrows, f, C, K, cams, num_views, S, nblocks, out_feat);      \
-    else                                                                                                           \
-        hipLaunchKernelGGL((topk_gather_lds_kernel<FT, TPP, W, kStagedK>), dim3((unsigned)nblocks),                \
+        hipLaunchKernelGGL((topk_gather_lds_kernel<FT, TPP, W, 8, LABEL>), dim3((unsigned)nblocks),               \
                            dim3(kGatherThreads), 0, s, pairs, counts, rows, nrows, f, C, K, cams, num_views, S,   \
-                           nblocks, out_feat)
+                           nblocks, out_feat, out_label, out_score);                                               \
+    else                                                                                                           \
+        hipLaunchKernelGGL((topk_gather_lds_kernel<FT, TPP, W, kStagedK, LABEL>), dim3((unsigned)nblocks),         \
+                           dim3(kGatherThreads), 0, s, pairs, counts, rows, nrows, f, C, K, cams, num_views, S,   \
+                           nblocks, out_feat, out_label, out_score)
         // row windows of 4-24 KB (32 rows of 512 B measured best for C = 128
         // float32 against 16, 24 and 40)
         switch (tpp) {
@@ -669,8 +744,9 @@ hipError_t launch_gather(const uint2* pairs, const int32_t* counts, const uint32
     const int64_t groups = nblocks * 64 * tpp / kGatherThreads;
     if (groups >= (int64_t(1) << 32)) return hipErrorInvalidValue;
 #define FS_GATHER(TPP)                                                                                            \
-    hipLaunchKernelGGL((topk_gather_general_kernel<FT, VE, TPP>), dim3((unsigned)groups), dim3(kGatherThreads), 0, \
-                       s, pairs, counts, rows, f, C, K, cams, num_views, S, groups, out_feat)
+    hipLaunchKernelGGL((topk_gather_general_kernel<FT, VE, TPP, LABEL>), dim3((unsigned)groups),                   \
+                       dim3(kGatherThreads), 0, s, pairs, counts, rows, f, C, K, cams, num_views, S, groups, out_feat, \
+                       out_label, out_score)
     switch (tpp) {
         case 4: FS_GATHER(4); break;
         case 8: FS_GATHER(8); break;
@@ -706,27 +782,29 @@ hipError_t fs_launch_topk_select(const FsRecord* records, const uint32_t* vals, 
 
 hipError_t fs_launch_render_topk_split(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges,
                                        const void* feats, int C, int64_t n, const fs_camera* cams, int num_views,
-                                       int64_t total_tiles, const fs_opts& o, float* out_feat, float* out_T,
-                                       int32_t* out_n, int32_t* out_last, int32_t* out_idx, uint64_t* counters,
-                                       const FsWorkspace& ws, hipStream_t s) {
+                                       int64_t total_tiles, const fs_opts& o, float* out_feat, int32_t* out_label,
+                                       float* out_score, float* out_T, int32_t* out_n, int32_t* out_last,
+                                       int32_t* out_idx, uint64_t* counters, const FsWorkspace& ws, hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
     const int sb = o.tile / 8;
     const int64_t nblocks = total_tiles * sb * sb;
     if (ws.topk_pairs == nullptr || ws.topk_rows == nullptr || ws.topk_nrows == nullptr ||
-        ws.topk_pair_slots < nblocks * 64 * (int64_t)o.topk ||
-        nblocks >= (int64_t(1) << 31))
+        ws.topk_pair_slots < nblocks * 64 * (int64_t)o.topk || nblocks >= (int64_t(1) << 31) ||
+        (out_feat == nullptr) == (out_label == nullptr))
         return hipErrorInvalidValue;
     hipError_t e = fs_launch_topk_select(records, vals, ranges, n, cams, num_views, total_tiles, o, out_T, out_n,
                                          out_last, out_idx, counters, ws, s);
     if (e != hipSuccess) return e;
     const bool bf16 = o.feat_dtype == FS_FEAT_BF16;
-    if (bf16)
-        return C % 8 == 0 ? launch_gather<uint16_t, 8>(ws.topk_pairs, out_n, ws.topk_rows, ws.topk_nrows, feats, C,
-                                                       o.topk, cams, num_views, o.tile, nblocks, out_feat, s)
-                          : launch_gather<uint16_t, 1>(ws.topk_pairs, out_n, ws.topk_rows, ws.topk_nrows, feats, C,
-                                                       o.topk, cams, num_views, o.tile, nblocks, out_feat, s);
-    return C % 4 == 0 ? launch_gather<float, 4>(ws.topk_pairs, out_n, ws.topk_rows, ws.topk_nrows, feats, C, o.topk,
-                                                cams, num_views, o.tile, nblocks, out_feat, s)
-                      : launch_gather<float, 1>(ws.topk_pairs, out_n, ws.topk_rows, ws.topk_nrows, feats, C, o.topk,
-                                                cams, num_views, o.tile, nblocks, out_feat, s);
+    const bool vec = C % (bf16 ? 8 : 4) == 0;
+#define FS_GATHER_FORM(FT, VE, LABEL)                                                                             \
+    launch_gather<FT, VE, LABEL>(ws.topk_pairs, out_n, ws.topk_rows, ws.topk_nrows, feats, C, o.topk, cams,      \
+                                 num_views, o.tile, nblocks, out_feat, out_label, out_score, s)
+    if (out_label) {
+        if (bf16) return vec ? FS_GATHER_FORM(uint16_t, 8, true) : FS_GATHER_FORM(uint16_t, 1, true);
+        return vec ? FS_GATHER_FORM(float, 4, true) : FS_GATHER_FORM(float, 1, true);
+    }
+    if (bf16) return vec ? FS_GATHER_FORM(uint16_t, 8, false) : FS_GATHER_FORM(uint16_t, 1, false);
+    return vec ? FS_GATHER_FORM(float, 4, false) : FS_GATHER_FORM(float, 1, false);
+#undef FS_GATHER_FORM
 }

@@ -176,6 +176,28 @@ class Rasterizer:
                 "fs_render_forward")
         return out
 
+    def render_labels(self, feats, *, out=None, want_score: bool = True, counters: torch.Tensor | None = None):
+        """Per-pixel argmax channel (and its value) of the Top-K render, from
+        the current sorted lists; needs the split schedule."""
+        n, C = feats.shape
+        if feats.dtype != (torch.bfloat16 if self.feat_dtype == "bf16" else torch.float32) or not feats.is_contiguous():
+            raise ValueError(f"feats must be contiguous {self.feat_dtype}")
+        b = self._bufs
+        dev = self.device
+        if out is None:
+            out = {
+                "label": torch.empty(self.total_pixels, dtype=torch.int32, device=dev),
+                "score": torch.empty(self.total_pixels, dtype=torch.float32, device=dev) if want_score else None,
+                "T": torch.empty(self.total_pixels, dtype=torch.float32, device=dev),
+                "n": torch.empty(self.total_pixels, dtype=torch.int32, device=dev),
+            }
+        L.check(self.lib.fs_render_labels(_p(b["records"]), _p(b["vals"]), _p(b["ranges"]), _p(feats), C, n,
+                                          _p(self.cams_dev), self.num_views, self.total_tiles,
+                                          ctypes.byref(self.opts), _p(out["label"]), _p(out["score"]), _p(out["T"]),
+                                          _p(out["n"]), _p(counters), _p(b["ws"]), _stream(dev)),
+                "fs_render_labels")
+        return out
+
     def render(self, means, scales, quats, opacity, feats, *, want_last: bool = False,
                want_idx: bool = False) -> Frame:
         n = means.shape[0]
@@ -218,7 +240,10 @@ class Rasterizer:
                                  self.total_tiles, _p(b["ranges"]), _p(b["ws"]), _stream(dev)), "fs_sort")
         if ev[3] is not None:
             ev[3].record()
-        self.render_forward(feats, out=out, counters=counters)
+        if "label" in out:   # an alloc_labels() dict: the label epilogue in place of the feature image
+            self.render_labels(feats, out=out, counters=counters)
+        else:
+            self.render_forward(feats, out=out, counters=counters)
         if ev[4] is not None:
             ev[4].record()
 
@@ -234,6 +259,15 @@ class Rasterizer:
             "last": torch.empty(self.total_pixels, dtype=torch.int32, device=dev) if want_last else None,
             "idx": (torch.empty((self.total_pixels, self.topk), dtype=torch.int32, device=dev)
                     if want_idx and self.topk > 0 else None),
+        }
+
+    def alloc_labels(self, want_score: bool = True) -> dict:
+        dev = self.device
+        return {
+            "label": torch.empty(self.total_pixels, dtype=torch.int32, device=dev),
+            "score": torch.empty(self.total_pixels, dtype=torch.float32, device=dev) if want_score else None,
+            "T": torch.empty(self.total_pixels, dtype=torch.float32, device=dev),
+            "n": torch.empty(self.total_pixels, dtype=torch.int32, device=dev),
         }
 
     def render_backward(self, means, scales, quats, opacity, feats, frame: Frame, grad_feat: torch.Tensor):

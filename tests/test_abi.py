@@ -72,3 +72,12 @@ def test_host_only_entry_points_without_gpu():
     assert lib.fs_preprocess(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 1,
                              ctypes.c_void_p(16), 1, ctypes.byref(o5), ctypes.c_void_p(16), ctypes.c_void_p(16),
                              ctypes.c_void_p(20), None) == _lib.FS_ERR_ARG
+    # labels: the split schedule only, and every required output
+    d = ctypes.c_void_p(256)
+    og = _lib.make_opts(topk=8, schedule=_lib.FS_SCHED_GRID)
+    assert lib.fs_render_labels(d, d, d, d, 16, 10, d, 1, 4, ctypes.byref(og), d, None, d, d, None, d,
+                                None) == _lib.FS_ERR_UNSUPPORTED
+    assert lib.fs_render_labels(d, d, d, d, 16, 10, d, 1, 4, ctypes.byref(o5), None, None, d, d, None, d,
+                                None) == _lib.FS_ERR_ARG
+    assert lib.fs_render_labels(d, d, d, d, 16, 10, d, 1, 4, ctypes.byref(o5), d, None, d, d, None, None,
+                                None) == _lib.FS_ERR_ARG

@@ -478,3 +478,82 @@ def test_topk_by_weight_invariants():
         np.testing.assert_allclose(rw.T, full.T, rtol=1e-12)
         assert np.all(rw.F[..., -1] >= rf.F[..., -1] - 1e-12)
         assert np.all(rw.n == np.minimum(K, full.n))
+
+
+# ---------------------------------------------------------------------------
+# Segmentation labels from the blended channels (Sec. 3.3, Sec. 3.5)
+# ---------------------------------------------------------------------------
+
+def _two_splats(o_front):
+    cam = scenes.Camera(8, 8, 8.0, 8.0, 4.0, 4.0)
+    sc = scenes.Scene(np.array([[0.0, 0.0, 4.0], [0.0, 0.0, 2.0]], np.float32),   # second one is in front
+                      np.array([[0.5, 0.5], [0.25, 0.25]], np.float32),
+                      np.array([[1, 0, 0, 0], [1, 0, 0, 0]], np.float32), np.array([0.5, o_front], np.float32),
+                      np.array([[0.0, 1.0, 0.0], [1.0, 0.0, 1.0]], np.float32))
+    return sc, cam
+
+
+def test_labels_two_splats_by_hand():
+    """At pixel (4, 4) F = (a_f, a_b (1 - a_f), a_f) with a = o exp(-1/4): the
+    front splat's channels 0 and 2 tie exactly and the lower one is the
+    label while a_f > a_b (1 - a_f); a faint front splat hands the label to
+    the back one's channel 1 unless Top-K (K = 1, first) drops the back one.
+    A pixel no splat reaches has F = 0 and label 0."""
+    sc, cam = _two_splats(0.8)
+    lab, score, near = oracle.labels(oracle.render_scene(sc, cam))
+    a_f = float(np.float32(0.8)) * np.exp(-0.25)
+    assert lab[4, 4] == 0 and score[4, 4] == pytest.approx(a_f, rel=1e-12)
+    assert list(near[4, 4]) == [True, False, True]
+    assert lab[0, 0] == 0 and score[0, 0] == 0.0
+    sc, cam = _two_splats(0.1)
+    a_f = float(np.float32(0.1)) * np.exp(-0.25)
+    a_b = 0.5 * np.exp(-0.25)
+    assert a_b * (1 - a_f) > a_f
+    lab, score, _ = oracle.labels(oracle.render_scene(sc, cam))
+    assert lab[4, 4] == 1 and score[4, 4] == pytest.approx(a_b * (1 - a_f), rel=1e-12)
+    lab1, score1, _ = oracle.labels(oracle.render_scene(sc, cam, K=1))
+    assert lab1[4, 4] == 0 and score1[4, 4] == pytest.approx(a_f, rel=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_labels_match_pure_python_brute_force(seed):
+    sc, cam = _tilted_scene(30, 30 + seed)
+    proj = oracle.project_scene(sc, cam)
+    rng = np.random.default_rng(seed)
+    pix = [(int(rng.integers(0, cam.width)), int(rng.integers(0, cam.height))) for _ in range(40)]
+    for K in (0, 3):
+        r = oracle.render_image(proj, sc.opacity, sc.feats, cam.width, cam.height, K=K)
+        lab, score, near = oracle.labels(r, 1e-9)
+        for (px, py), (F, _, _) in zip(pix, _indep.brute_blend(sc, cam, pix, K=K)):
+            best = 0
+            for c in range(1, len(F)):
+                if F[c] > F[best]:
+                    best = c
+            if r.amb[py, px] or near[py, px].sum() > 1:
+                continue
+            assert lab[py, px] == best
+            assert score[py, px] == pytest.approx(F[best], rel=1e-9, abs=1e-12)
+
+
+def test_labels_invariants():
+    """Adding one constant to every channel of every surfel shifts all
+    channels of F by the same amount; scaling by a power of two scales F
+    exactly; permuting channels permutes labels."""
+    sc, cam = scenes.parity_small()
+    proj = oracle.project_scene(sc, cam)
+    C = sc.channels
+    base = oracle.render_image(proj, sc.opacity, sc.feats, cam.width, cam.height, K=8)
+    lab, score, near = oracle.labels(base, 1e-9)
+    hit = base.n > 0
+    sure = (near.sum(-1) == 1) & (base.amb == 0) & hit
+    assert sure[hit].mean() > 0.9 and hit.mean() > 0.3
+    assert np.all(lab[~hit] == 0) and np.all(score[~hit] == 0.0)
+    shifted = oracle.render_image(proj, sc.opacity, sc.feats + np.float32(3.0), cam.width, cam.height, K=8)
+    assert np.array_equal(oracle.labels(shifted)[0][sure], lab[sure])
+    scaled = oracle.render_image(proj, sc.opacity, sc.feats * np.float32(4.0), cam.width, cam.height, K=8)
+    l4, s4, _ = oracle.labels(scaled)
+    assert np.array_equal(l4, lab) and np.array_equal(s4, 4.0 * score)
+    perm = np.random.default_rng(5).permutation(C)
+    permuted = oracle.render_image(proj, sc.opacity, sc.feats[:, perm], cam.width, cam.height, K=8)
+    inv = np.argsort(perm)   # channel c of the original is channel inv[c] of the permuted scene
+    assert np.array_equal(oracle.labels(permuted)[0][sure], inv[lab[sure]])
