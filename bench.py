@@ -135,10 +135,13 @@ def form_topk_weight(dev, steps, warmup):
     return res
 
 
-def form_labels(scene_tens, dev, steps, warmup):
+def form_labels(scene, scene_tens, dev, steps, warmup):
     """Segmentation labels (per-pixel argmax channel and its score) of the
     1M-surfel, 1280x720, C = 128, K = 8 frame: the split render with the label
-    epilogue against the same frame writing its feature image."""
+    epilogue against the same frame writing its feature image.  Then the
+    instance pipeline: per-Gaussian instance labels from 32 queries of
+    dimension 32 (one launch over the 1M Gaussians) and the label frame that
+    blends those 32 channels into a per-pixel instance id."""
     cam = scenes.centred_camera(1280, 720)
     rast = raster.Rasterizer(cam, tile=8, topk=8, schedule="split", device=dev)
     fr = rast.render(*scene_tens)
@@ -155,6 +158,46 @@ def form_labels(scene_tens, dev, steps, warmup):
                 "labels_render_algorithmic_bytes": nbytes,
                 "labels_render_hbm_frac": nbytes / (lab_st["render"] * 1e-3) / 1e9 / HBM_PEAK_GBS})
     del rast, fr, lab
+    torch.cuda.empty_cache()
+    Q = DQ = 32
+    fi, q = scenes.instance_inputs(scene, Q, DQ)
+    ti = [torch.from_numpy(a).to(dev) for a in (fi, q.feats, q.means, q.covs)]
+    lab_i = torch.empty((scene.n, Q), dtype=torch.float32, device=dev)
+
+    def inst():
+        raster.instance_labels(ti[0], scene_tens[0], ti[1], ti[2], ti[3], out=lab_i)
+
+    for _ in range(warmup):
+        inst()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        inst()
+    b.record()
+    torch.cuda.synchronize()
+    inst_ms = a.elapsed_time(b) / steps
+    inst_bytes = scene.n * (4 * DQ + 12 + 4 * Q)
+    rast = raster.Rasterizer(cam, tile=8, topk=8, schedule="split", device=dev)
+    rast.render(*scene_tens[:4], lab_i)
+    out = rast.alloc_labels()
+    for _ in range(warmup):
+        inst()
+        rast.render_nosync(*scene_tens[:4], lab_i, out)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps):
+        inst()
+        rast.render_nosync(*scene_tens[:4], lab_i, out)
+    b.record()
+    torch.cuda.synchronize()
+    if not rast.pairs_fit():
+        raise RuntimeError("pair capacity exceeded")
+    res.update({"instance_queries": Q, "instance_dim": DQ, "instance_labels_ms": inst_ms,
+                "instance_labels_hbm_frac": inst_bytes / (inst_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "instance_frame_ms": a.elapsed_time(b) / steps,
+                "instance_frame_fps": 1e3 * steps / a.elapsed_time(b)})
+    del rast, out, lab_i, ti
     torch.cuda.empty_cache()
     return res
 
@@ -307,7 +350,7 @@ def main():
             res = form_topk_weight(dev, fs, fw)
         elif args.form == "labels":
             scene, _ = scenes.headline(seed=args.seed, channels=C)
-            res = form_labels(raster.scene_tensors(scene, dev), dev, fs, fw)
+            res = form_labels(scene, raster.scene_tensors(scene, dev), dev, fs, fw)
         else:
             scene, _ = scenes.headline(seed=args.seed, channels=C)
             res = form_batched(raster.scene_tensors(scene, dev), dev, fs, fw)
@@ -381,7 +424,7 @@ def main():
         print("[bench] form: batched views", file=sys.stderr, flush=True)
         forms = {"batched": form_batched(tens, dev, fs, fw)}
         print("[bench] form: labels", file=sys.stderr, flush=True)
-        forms["labels"] = form_labels(tens, dev, fs, fw)
+        forms["labels"] = form_labels(scene, tens, dev, fs, fw)
         del tens
         torch.cuda.empty_cache()
         print("[bench] form: backward", file=sys.stderr, flush=True)

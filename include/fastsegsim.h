@@ -18,6 +18,9 @@
  *                       (Sec. 3.4, F_TopK)
  *   fs_render_labels    the same render reduced per pixel to the argmax channel
  *                       and its value (segmentation masks, Sec. 3.3, 3.5)
+ *   fs_instance_labels  per-Gaussian instance labels from instance queries
+ *                       (feature similarity x spatial proximity, softmax;
+ *                       Sec. 3.3): the channels the label render blends
  *   fs_render_backward  gradients of a loss on the rendered features w.r.t.
  *                       surfel centres, scales, rotations, opacities and
  *                       features (the renderer is trained end to end, Sec. 3.5)
@@ -249,6 +252,34 @@ fs_status fs_render_labels(const void* records, const uint32_t* vals, const uint
                            int32_t C, int64_t n, const fs_camera* cams_dev, int32_t num_views, int64_t total_tiles,
                            const fs_opts* opts, int32_t* out_label, float* out_score, float* out_T, int32_t* out_n,
                            uint64_t* counters, void* workspace, hipStream_t stream);
+
+/*
+ * fs_instance_labels (Sec. 3.3, query-guided instance segmentation).  Per
+ * scene Gaussian g (centre p_g, instance feature f_g) and query q (feature
+ * f_q, 3D Gaussian with centre p_q and covariance Sigma_q):
+ *   S(q, g) = sigmoid(f_q . f_g)
+ *   D(q, g) = phi_q(p_g) / phi_q(p_q) = exp(-(p_g - p_q)^T Sigma_q^-1 (p_g - p_q) / 2)
+ *   out[g, :] = softmax over q of A(q, g) = S D
+ * The Q outputs per Gaussian are the instance-label channels the renderers
+ * blend (fs_render_forward / fs_render_labels with C = Q).  Float32 math
+ * (the Cholesky factor of each Sigma_q in double).
+ *   ins_feats     n x dim float32, rows 16-byte aligned (dim % 4 == 0)
+ *   means         n x 3 float32 Gaussian centres (the scene's means)
+ *   query_feats   num_queries x dim float32, 16-byte aligned
+ *   query_means   num_queries x 3 float32
+ *   query_covs    num_queries x 6 float32 symmetric covariances (xx, xy, xz,
+ *                 yy, yz, zz), positive definite (otherwise the outputs of
+ *                 every Gaussian are NaN)
+ *   out_labels    out, n x num_queries float32 (16-byte aligned when
+ *                 num_queries % 4 == 0); each row sums to 1
+ * n == 0 enqueues nothing.  FS_ERR_ARG for null pointers, misalignment or
+ * dim / num_queries < 1; FS_ERR_UNSUPPORTED for dim % 4 != 0 or num_queries
+ * > FS_MAX_QUERIES.
+ */
+#define FS_MAX_QUERIES 64
+fs_status fs_instance_labels(const float* ins_feats, int32_t dim, const float* means, int64_t n,
+                             const float* query_feats, const float* query_means, const float* query_covs,
+                             int32_t num_queries, float* out_labels, hipStream_t stream);
 
 /*
  * fs_render_backward.  Given dL/dF (grad_feat, total_pixels x C float32) for

@@ -17,6 +17,8 @@ Functions and the paper passage each follows:
                  front-to-back blend, full or Top-K            Sec. 3.1 Eq. (2), Sec. 3.4 F_TopK
   labels         per-pixel argmax channel of a render          Sec. 3.3, Sec. 3.5 (masks from blended
                                                                class / instance channels)
+  query_density_ratio / instance_labels
+                 per-Gaussian instance labels from queries    Sec. 3.3 (S, D, A, softmax)
   render_grad    chain rule of the blend (held decisions)     training through the renderer, Sec. 3.5
   finite_difference  central differences of render_image      (pins render_grad)
 
@@ -296,6 +298,39 @@ def labels(r: Render, rel_tol: float = 0.0):
     lo = score - rel_tol * np.take_along_axis(A, label[..., None], axis=-1)[..., 0]
     near = F + rel_tol * A >= lo[..., None]
     return label, score, near
+
+
+def _cov_matrix(c6) -> np.ndarray:
+    xx, xy, xz, yy, yz, zz = (float(v) for v in c6)
+    return np.array([[xx, xy, xz], [xy, yy, yz], [xz, yz, zz]])
+
+
+def query_density_ratio(points, query_mean, query_cov6) -> np.ndarray:
+    """D(p_q, p_g) = phi(p_g) / phi(p_q) (Sec. 3.3), phi the density of the
+    query's Gaussian N(p_q, Sigma_q), each evaluated in full (normalising
+    constant included) and then divided."""
+    S = _cov_matrix(query_cov6)
+    P = np.linalg.inv(S)
+    norm = 1.0 / np.sqrt((2.0 * np.pi) ** 3 * np.linalg.det(S))
+    mu = _f64(query_mean).reshape(3)
+
+    def phi(x):
+        d = x - mu
+        return norm * np.exp(-0.5 * np.einsum("ni,ij,nj->n", d, P, d))
+
+    return phi(_f64(points).reshape(-1, 3)) / phi(mu[None])
+
+
+def instance_labels(ins_feats, means, query_feats, query_means, query_covs) -> np.ndarray:
+    """Instance label of every scene Gaussian (Sec. 3.3), in double precision:
+    similarity S = sigmoid(f_q^T f_ins), proximity D = query_density_ratio,
+    attention A = S D, label = softmax of A over the queries.  Returns
+    (n, Q)."""
+    f, fq = _f64(ins_feats), _f64(query_feats)
+    S = 1.0 / (1.0 + np.exp(-(f @ fq.T)))
+    D = np.stack([query_density_ratio(means, query_means[q], query_covs[q]) for q in range(fq.shape[0])], axis=1)
+    E = np.exp(S * D)
+    return E / E.sum(axis=1, keepdims=True)
 
 
 @dataclass

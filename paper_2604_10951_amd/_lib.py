@@ -65,6 +65,7 @@ SIGNATURES = {
     "fs_sort": ([P, P, I64, P, I64, I64, P, P, P], I32),
     "fs_render_forward": ([P, P, P, P, I32, I64, P, I32, I64, ctypes.POINTER(FsOpts), P, P, P, P, P, P, P, P], I32),
     "fs_render_labels": ([P, P, P, P, I32, I64, P, I32, I64, ctypes.POINTER(FsOpts), P, P, P, P, P, P, P], I32),
+    "fs_instance_labels": ([P, I32, P, I64, P, P, P, I32, P, P], I32),
     "fs_render_backward": ([P, P, P, P, P, P, P, P, I32, I64, P, I32, I64, ctypes.POINTER(FsOpts), P, P, P, P, P, P,
                             P, P, P, P, P, P], I32),
     "fs_status_string": ([I32], ctypes.c_char_p),

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfastsegsim.so")
-SOURCES = ["api.hip", "preprocess.hip", "bin.hip", "sort.hip", "render_fwd.hip", "render_topk.hip", "render_bwd.hip"]
+SOURCES = ["api.hip", "preprocess.hip", "bin.hip", "sort.hip", "render_fwd.hip", "render_topk.hip", "render_bwd.hip",
+           "instance.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -220,6 +220,20 @@ fs_status fs_render_labels(const void* records, const uint32_t* vals, const uint
                                                   out_score, out_T, out_n, nullptr, nullptr, counters, ws, stream));
 }
 
+fs_status fs_instance_labels(const float* ins_feats, int32_t dim, const float* means, int64_t n,
+                             const float* query_feats, const float* query_means, const float* query_covs,
+                             int32_t num_queries, float* out_labels, hipStream_t stream) {
+    if (n < 0 || dim < 1 || num_queries < 1) return FS_ERR_ARG;
+    if (!ins_feats || !means || !query_feats || !query_means || !query_covs || !out_labels) return FS_ERR_ARG;
+    if (dim % 4 != 0 || num_queries > FS_MAX_QUERIES) return FS_ERR_UNSUPPORTED;
+    const uintptr_t out_align = num_queries % 4 == 0 ? 16 : 4;
+    if ((uintptr_t)ins_feats % 16 || (uintptr_t)query_feats % 16 || (uintptr_t)out_labels % out_align ||
+        (uintptr_t)means % 4 || (uintptr_t)query_means % 4 || (uintptr_t)query_covs % 4)
+        return FS_ERR_ARG;
+    return hip_status(fs_launch_instance_labels(ins_feats, dim, means, n, query_feats, query_means, query_covs,
+                                                num_queries, out_labels, stream));
+}
+
 fs_status fs_render_backward(const float* means, const float* scales, const float* quats, const float* opacity,
                              const void* records, const uint32_t* vals, const uint32_t* tile_ranges,
                              const void* feats, int32_t C, int64_t n, const fs_camera* cams_dev, int32_t num_views,

@@ -664,6 +664,11 @@ hipError_t fs_launch_topk_select(const FsRecord* records, const uint32_t* vals, 
                                  float* out_T, int32_t* out_n, int32_t* out_last, int32_t* out_idx,
                                  uint64_t* counters, const FsWorkspace& ws, hipStream_t s);
 
+// Per-Gaussian instance labels (softmax over queries of similarity x
+// proximity); 1 <= Q <= FS_MAX_QUERIES, D % 4 == 0.
+hipError_t fs_launch_instance_labels(const float* fins, int D, const float* means, int64_t n, const float* fq,
+                                     const float* qmeans, const float* qcovs, int Q, float* out, hipStream_t s);
+
 // Both passes of the split Top-K renderer.  Exactly one of out_feat (feature
 // image) and out_label (per-pixel channel argmax, out_score optional) is set.
 hipError_t fs_launch_render_topk_split(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges,

@@ -299,3 +299,42 @@ def crop_near_cluster(scene: Scene, count: int, cluster: int = 0) -> np.ndarray:
     assert scene.centres is not None
     d = np.linalg.norm(scene.means.astype(np.float64) - scene.centres[cluster].astype(np.float64), axis=1)
     return np.sort(np.argsort(d, kind="stable")[:count])
+
+
+@dataclass
+class Queries:
+    feats: np.ndarray   # (Q, D) float32 query features
+    means: np.ndarray   # (Q, 3) float32 query centres
+    covs: np.ndarray    # (Q, 6) float32 covariances (xx, xy, xz, yy, yz, zz)
+
+
+def instance_inputs(scene: Scene, num_queries: int = 32, dim: int = 32, *, seed: int = 0,
+                    sigma: float = 0.6) -> tuple[np.ndarray, Queries]:
+    """Instance features for every surfel and instance queries (the inputs of
+    the query-guided instance labels, Sec. 3.3; the paper uses 32-dimensional
+    features).  Query j sits at a cluster centre (or a random surfel of an
+    unclustered scene) with a random covariance R diag(s^2) R^T, s in
+    sigma * [0.5, 2]; its feature is a random unit vector times 3.  A surfel's
+    feature is the feature of the query of its cluster (cluster id mod Q;
+    nearest query centre for unclustered scenes) plus N(0, 0.5^2) noise."""
+    rng = np.random.default_rng(seed + 7919)
+    Q, n = num_queries, scene.n
+    if scene.centres is not None and scene.cluster is not None:
+        centres = scene.centres[np.arange(Q) % len(scene.centres)].astype(np.float64)
+        owner = scene.cluster % Q
+    else:
+        centres = scene.means[rng.integers(0, n, Q)].astype(np.float64)
+        d2 = ((scene.means[:, None, :].astype(np.float64) - centres[None]) ** 2).sum(-1)
+        owner = np.argmin(d2, axis=1)
+    covs = np.empty((Q, 6))
+    for j in range(Q):
+        a = rng.standard_normal((3, 3))
+        R, _ = np.linalg.qr(a)
+        s = sigma * rng.uniform(0.5, 2.0, 3)
+        S = (R * s ** 2) @ R.T
+        covs[j] = [S[0, 0], S[0, 1], S[0, 2], S[1, 1], S[1, 2], S[2, 2]]
+    qf = rng.standard_normal((Q, dim))
+    qf = 3.0 * qf / np.linalg.norm(qf, axis=1, keepdims=True)
+    feats = qf[owner] + 0.5 * rng.standard_normal((n, dim))
+    return (np.ascontiguousarray(feats, np.float32),
+            Queries(qf.astype(np.float32), centres.astype(np.float32), covs.astype(np.float32)))

@@ -81,3 +81,12 @@ def test_host_only_entry_points_without_gpu():
                                 None) == _lib.FS_ERR_ARG
     assert lib.fs_render_labels(d, d, d, d, 16, 10, d, 1, 4, ctypes.byref(o5), d, None, d, d, None, None,
                                 None) == _lib.FS_ERR_ARG
+    # instance labels: argument checks, and n == 0 enqueues nothing
+    a16 = ctypes.c_void_p(4096)
+    assert lib.fs_instance_labels(a16, 32, a16, 0, a16, a16, a16, 8, a16, None) == _lib.FS_OK
+    assert lib.fs_instance_labels(a16, 32, a16, 10, a16, a16, a16, 65, a16, None) == _lib.FS_ERR_UNSUPPORTED
+    assert lib.fs_instance_labels(a16, 6, a16, 10, a16, a16, a16, 8, a16, None) == _lib.FS_ERR_UNSUPPORTED
+    assert lib.fs_instance_labels(a16, 32, a16, 10, a16, a16, a16, 0, a16, None) == _lib.FS_ERR_ARG
+    assert lib.fs_instance_labels(ctypes.c_void_p(4100), 32, a16, 10, a16, a16, a16, 8, a16, None) == _lib.FS_ERR_ARG
+    assert lib.fs_instance_labels(a16, 32, a16, 10, a16, a16, a16, 8, ctypes.c_void_p(4100), None) == _lib.FS_ERR_ARG
+    assert lib.fs_instance_labels(a16, 32, None, 10, a16, a16, a16, 8, a16, None) == _lib.FS_ERR_ARG

@@ -557,3 +557,58 @@ def test_labels_invariants():
     permuted = oracle.render_image(proj, sc.opacity, sc.feats[:, perm], cam.width, cam.height, K=8)
     inv = np.argsort(perm)   # channel c of the original is channel inv[c] of the permuted scene
     assert np.array_equal(oracle.labels(permuted)[0][sure], inv[lab[sure]])
+
+
+# ---------------------------------------------------------------------------
+# Query-guided instance labels (Sec. 3.3)
+# ---------------------------------------------------------------------------
+
+def test_query_density_ratio_matches_scipy():
+    """D = phi(p_g) / phi(p_q) against scipy's multivariate normal density for
+    anisotropic covariances (catches a misplaced off-diagonal entry)."""
+    from scipy.stats import multivariate_normal
+    rng = np.random.default_rng(3)
+    for _ in range(4):
+        A = rng.standard_normal((3, 3))
+        S = A @ A.T + 0.3 * np.eye(3)
+        mu = rng.standard_normal(3)
+        pts = mu + rng.standard_normal((50, 3))
+        c6 = [S[0, 0], S[0, 1], S[0, 2], S[1, 1], S[1, 2], S[2, 2]]
+        mvn = multivariate_normal(mean=mu, cov=S)
+        np.testing.assert_allclose(oracle.query_density_ratio(pts, mu, c6), mvn.pdf(pts) / mvn.pdf(mu),
+                                   rtol=1e-10)
+
+
+def test_instance_labels_two_queries_by_hand():
+    """Isotropic queries sigma^2 I at distances r1, r2 from the Gaussian and
+    feature products 2 and -1: A_j = sigmoid(dot_j) exp(-r_j^2 / (2 sigma_j^2)),
+    l = softmax(A)."""
+    f = np.array([[1.0, 0.0, 0.0, 0.0]])
+    p = np.array([[0.0, 0.0, 0.0]])
+    fq = np.array([[2.0, 5.0, 0.0, 0.0], [-1.0, 0.0, 3.0, 0.0]])
+    pq = np.array([[0.3, 0.0, 0.0], [0.0, -0.2, 0.4]])
+    s1, s2 = 0.5, 0.8
+    covs = np.array([[s1 ** 2, 0, 0, s1 ** 2, 0, s1 ** 2], [s2 ** 2, 0, 0, s2 ** 2, 0, s2 ** 2]])
+    a1 = 1 / (1 + np.exp(-2.0)) * np.exp(-0.09 / (2 * s1 ** 2))
+    a2 = 1 / (1 + np.exp(1.0)) * np.exp(-0.2 / (2 * s2 ** 2))
+    want = np.array([np.exp(a1), np.exp(a2)]) / (np.exp(a1) + np.exp(a2))
+    np.testing.assert_allclose(oracle.instance_labels(f, p, fq, pq, covs)[0], want, rtol=1e-13)
+
+
+def test_instance_labels_invariants():
+    """Rows sum to 1; one query gives label 1; permuting the queries permutes
+    the columns; a Gaussian sitting on a query whose feature it matches
+    strongly gets that query's largest label."""
+    scene, _ = scenes.parity_small()
+    f, q = scenes.instance_inputs(scene, 7, 12)
+    lab = oracle.instance_labels(f, scene.means, q.feats, q.means, q.covs)
+    np.testing.assert_allclose(lab.sum(1), 1.0, rtol=1e-13)
+    assert np.all(lab > 0)
+    one = oracle.instance_labels(f, scene.means, q.feats[:1], q.means[:1], q.covs[:1])
+    np.testing.assert_allclose(one, 1.0, rtol=1e-15)
+    perm = np.array([3, 0, 6, 1, 5, 2, 4])
+    lp = oracle.instance_labels(f, scene.means, q.feats[perm], q.means[perm], q.covs[perm])
+    np.testing.assert_allclose(lp, lab[:, perm], rtol=1e-13)
+    g = np.concatenate([f[:1], 10.0 * q.feats[2:3]])
+    pos = np.concatenate([scene.means[:1], q.means[2:3]])
+    assert np.argmax(oracle.instance_labels(g, pos, q.feats, q.means, q.covs)[1]) == 2
