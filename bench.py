@@ -202,6 +202,30 @@ def form_labels(scene, scene_tens, dev, steps, warmup):
     return res
 
 
+def form_ablation(scene_tens, dev, steps, warmup):
+    """The four rows of the paper's Tab. 2 on the 1M-surfel, 1280x720, C = 128
+    frame (8x8 tiles): (A) bounding-box tile assignment + full blend, (B)
+    precise tile intersection + full blend, (C) bounding box + Top-K K = 8,
+    (D) both.  Per row: frame time, listed (tile, surfel) pairs (RN-Total),
+    pairs per tile, list entries the render walks, and blended pairs."""
+    cam = scenes.centred_camera(1280, 720)
+    rows = {}
+    for name, mode, topk in (("A_baseline", "bbox", 0), ("B_precise_tiles", "precise", 0), ("C_topk", "bbox", K),
+                             ("D_precise_tiles_topk", "precise", K)):
+        rast = raster.Rasterizer(cam, tile=8, topk=topk, tile_mode=mode, device=dev)
+        fr = rast.render(*scene_tens)
+        cnt = render_counters(rast, scene_tens, rast.alloc_out(C))
+        ms = _time_frames(rast, scene_tens, steps, warmup)
+        T = rast.total_tiles
+        rows[name] = {"tile_mode": mode, "topk": topk, "time_ms": ms, "fps": 1e3 / ms, "pairs": fr.num_pairs,
+                      "pairs_per_tile": fr.num_pairs / T, "walked": cnt["walked"], "walked_per_tile": cnt["walked"] / T,
+                      "blended": cnt["blended"]}
+        del rast, fr
+        torch.cuda.empty_cache()
+    return {"workload": "1M surfels, 1280x720, C=128, 8x8 tiles; full blend: fused grid schedule, Top-K K=8: split",
+            "tiles": int((1280 // 8) * (720 // 8)), "rows": rows}
+
+
 def form_batched(scene_tens, dev, steps, warmup):
     """1M surfels, 16 look-at views of uneven resolution, C = 128, K = 8: one
     hipGraph replay of the batched frame (split Top-K render: measured 4.1 ms
@@ -330,7 +354,7 @@ def main():
     ap.add_argument("--schedule", default="split", choices=("grid", "persistent", "split"),
                     help="render schedule of the Top-K frames (the full blend uses 'grid')")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 / batched / backward forms")
-    ap.add_argument("--form", choices=("batched", "backward", "bf16", "topk_weight", "labels"), default=None,
+    ap.add_argument("--form", choices=("batched", "backward", "bf16", "topk_weight", "labels", "ablation"), default=None,
                     help="run only this form and print its JSON line (profiling)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer 3 times (reference for HBM byte counters)")
@@ -348,6 +372,9 @@ def main():
             res = form_bf16(dev, fs, fw)
         elif args.form == "topk_weight":
             res = form_topk_weight(dev, fs, fw)
+        elif args.form == "ablation":
+            scene, _ = scenes.headline(seed=args.seed, channels=C)
+            res = form_ablation(raster.scene_tensors(scene, dev), dev, fs, fw)
         elif args.form == "labels":
             scene, _ = scenes.headline(seed=args.seed, channels=C)
             res = form_labels(scene, raster.scene_tensors(scene, dev), dev, fs, fw)
@@ -423,6 +450,8 @@ def main():
         fs, fw = 10, 2
         print("[bench] form: batched views", file=sys.stderr, flush=True)
         forms = {"batched": form_batched(tens, dev, fs, fw)}
+        print("[bench] form: Tab. 2 ablation", file=sys.stderr, flush=True)
+        forms["ablation"] = form_ablation(tens, dev, fs, fw)
         print("[bench] form: labels", file=sys.stderr, flush=True)
         forms["labels"] = form_labels(scene, tens, dev, fs, fw)
         del tens
