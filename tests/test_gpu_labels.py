@@ -85,6 +85,10 @@ def _check_against_oracle(rast, lab, ref, v, pixels, name):
     ("bf16", 125, 8, "first"),    # bfloat16 rows, 8 channels per vector
     ("f32", 297, 4, "first"),     # C = 300: more vectors than lanes, general gather
     ("f32", 61, 8, "weight"),     # Top-K by weight
+    ("f32", 5, 4, "first"),       # C = 8: 4 threads per pixel
+    ("f32", 29, 8, "first"),      # C = 32: 8 threads per pixel
+    ("f32", 253, 8, "first"),     # C = 256: 64 threads per pixel (the reduction crosses wave halves)
+    ("bf16", 509, 16, "first"),   # C = 512 bfloat16: 64 threads per pixel, K = 16
 ])
 def test_labels_small_against_features_and_oracle(dtype, channels, K, mode):
     _case(f"labels small {dtype} C={channels + 3} K={K} {mode}")
