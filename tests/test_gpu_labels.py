@@ -7,8 +7,6 @@ transmittance and counts bit for bit), and against the oracle's labels on
 every pixel whose label the float32 tolerance cannot flip."""
 from __future__ import annotations
 
-import ctypes
-
 import numpy as np
 import pytest
 import torch
