@@ -342,7 +342,6 @@ def instance_labels(ins_feats: torch.Tensor, means: torch.Tensor, query_feats: t
                     query_means: torch.Tensor, query_covs: torch.Tensor, out: torch.Tensor | None = None):
     """Per-Gaussian instance labels, n x Q float32 (softmax over the queries of
     feature similarity x spatial proximity), computed by fs_instance_labels."""
-    lib = L.load()
     n, dim = ins_feats.shape
     Q = query_feats.shape[0]
     _f32(ins_feats, (n, dim), "ins_feats")
@@ -350,6 +349,7 @@ def instance_labels(ins_feats: torch.Tensor, means: torch.Tensor, query_feats: t
     _f32(query_feats, (Q, dim), "query_feats")
     _f32(query_means, (Q, 3), "query_means")
     _f32(query_covs, (Q, 6), "query_covs")
+    lib = L.load()
     if out is None:
         out = torch.empty((n, Q), dtype=torch.float32, device=ins_feats.device)
     L.check(lib.fs_instance_labels(_p(ins_feats), dim, _p(means), n, _p(query_feats), _p(query_means),
