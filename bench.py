@@ -4,8 +4,12 @@ Workload: 1,000,000 clustered 2D Gaussian surfels (20x20x5 box, 50 clusters),
 one 1280x720 pinhole view (fx = fy = 1280), 128 float32 feature channels,
 8x8 binning tiles.  One step = the whole path for one frame: preprocess
 (projection, culling, precise tile counts) -> bin (scan + key emission) ->
-sort (radix sort + tile ranges) -> render forward.  The headline value is the
-Top-K (K = 8) frame rate; the full blend on the same scene is timed beside it.
+sort (per-tile sort + tile ranges) -> render forward.  The headline value is
+the Top-K (K = 8) frame rate; the full blend on the same scene is timed beside
+it.  The line also carries the render's HBM roofline figures, the CPU oracle
+timed on the host, and the forms: batched multi-view graph, backward,
+bfloat16, Top-K by weight, labels (argmax epilogue and query-guided instance
+labels) and the four-row tile/blend ablation (`--form NAME` runs one alone).
 
 Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
