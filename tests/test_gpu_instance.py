@@ -56,7 +56,10 @@ def _check(got, feats, means, q, name):
 
 
 @pytest.mark.parametrize("n,Q,D", [(1000, 1, 32), (1000, 5, 32), (1000, 8, 4), (1777, 32, 32), (300, 64, 36),
-                                   (257, 13, 16)])
+                                   (257, 13, 16),
+                                   (1, 32, 32),     # matrix-core form, one live lane of 64
+                                   (63, 32, 32),    # matrix-core form, a partial wave
+                                   (500, 32, 48)])  # Q = 32 with another dimension: the vector form
 def test_instance_labels_small(n, Q, D):
     _case(f"instance labels n={n} Q={Q} D={D}")
     scene = scenes.uniform_scene(n, seed=Q + D)
