@@ -1,6 +1,6 @@
 """GPU parity: the HIP path against the CPU oracle on the same seeded inputs.
 
-Bars (the benchmark spec): tile counts, sorted keys/values and tile ranges
+Bars: tile counts, sorted keys/values and tile ranges
 bit-exact; Top-K index sets exact; float32 images within 1e-5 relative to
 the pixel's absolute-term sum sum_i w_i |c_i| (the scale of float32 rounding
 in the blend), on every pixel whose threshold decisions are not within 1e-5
@@ -17,7 +17,7 @@ from paper_2604_10951_amd import raster, scenes
 
 pytestmark = pytest.mark.gpu
 
-REL_TOL = 1e-5          # spec tolerance for float32 images
+REL_TOL = 1e-5          # tolerance for float32 images, relative to the absolute-term sum
 T_TOL = 1e-5            # final transmittance, relative
 MASKED_MAX = 0.01       # at most 1% of pixels may sit within 1e-5 of a threshold
 
