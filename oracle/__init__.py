@@ -12,6 +12,9 @@ Functions and the paper passage each follows:
   project        tangent frame, T, adj(T), cutoff, culling    Sec. 3.1 Eq. (1), Sec. 3.2 (T)
   tile_sets      per-pixel footprint test -> tiles            Sec. 3.2 (exact result of the
                                                                precise tile intersection)
+  linearised_cov / linearised_tile_stats
+                 the linearised projected covariance Sigma' and what tiles it misses
+                                                               Sec. 3.2 (the printed formula, read literally)
   sort_pairs     (tile, depth) ordering                        Sec. 3.1 (depth-sorted surfels)
   render_image / render_pixels
                  front-to-back blend, full or Top-K            Sec. 3.1 Eq. (2), Sec. 3.4 F_TopK
@@ -169,6 +172,50 @@ def tile_sets(proj: Projection, width: int, height: int, tile: int, *, prefilter
                           _ptr(flags, _i8), _ptr(keys, _u64), _ptr(vals, _u32))
         keys, vals = keys[:total], vals[:total]
     return counts, flags, keys, vals
+
+
+def linearised_cov(T) -> tuple[np.ndarray, np.ndarray]:
+    """Screen-space centre mu and covariance Sigma' = J J^T of one surfel from
+    the local linearisation of Sec. 3.2 (its printed formula is garbled; read
+    as the Jacobian of the projective map at the tangent origin):
+    J[r, c] = (T[r, c] - mu_r T[w, c]) / T[w, 3] for r, c in {1, 2}, with
+    mu_r = T[r, 3] / T[w, 3].  The surfel's tangent coordinates have unit
+    variance (its scales are inside T)."""
+    T = np.asarray(T, np.float64)
+    mu = T[:2, 2] / T[2, 2]
+    J = (T[:2, :2] - mu[:, None] * T[2, :2][None, :]) / T[2, 2]
+    return mu, J @ J.T
+
+
+def linearised_tile_stats(proj: Projection, width: int, height: int, tile: int) -> dict:
+    """Tiles assigned by the linearised ellipse (x - mu)^T Sigma'^-1 (x - mu)
+    <= k^2 (pixel centres inside it, as the exact assignment uses the exact
+    footprint) against the exact per-pixel footprint d^2 <= k^2.  Counts:
+    exact_pairs / lin_pairs (tile, surfel) pairs of each assignment; dropped =
+    (surfel, pixel) contributions whose tile the linearised set lacks; extra =
+    linearised tiles holding no exact pixel; affected = pixels losing at least
+    one contribution; contributions = all exact (surfel, pixel) pairs."""
+    ys, xs = np.mgrid[0:height, 0:width]
+    cx, cy = xs + 0.5, ys + 0.5
+    tile_of = (ys // tile) * ((width + tile - 1) // tile) + (xs // tile)
+    out = {"exact_pairs": 0, "lin_pairs": 0, "dropped": 0, "extra": 0, "contributions": 0}
+    affected = np.zeros((height, width), bool)
+    for i in np.nonzero(proj.valid)[0]:
+        ex = surfel_d2_image(proj.H[i], width, height) <= proj.k2[i]
+        mu, S = linearised_cov(proj.T[i])
+        P = np.linalg.inv(S)
+        dx, dy = cx - mu[0], cy - mu[1]
+        lin = P[0, 0] * dx * dx + 2.0 * P[0, 1] * dx * dy + P[1, 1] * dy * dy <= proj.k2[i]
+        ex_t, lin_t = np.unique(tile_of[ex]), np.unique(tile_of[lin])
+        out["exact_pairs"] += len(ex_t)
+        out["lin_pairs"] += len(lin_t)
+        out["extra"] += len(np.setdiff1d(lin_t, ex_t))
+        drop = ex & ~np.isin(tile_of, lin_t)
+        out["dropped"] += int(drop.sum())
+        out["contributions"] += int(ex.sum())
+        affected |= drop
+    out["affected"] = int(affected.sum())
+    return out
 
 
 def sort_pairs(keys: np.ndarray, vals: np.ndarray):

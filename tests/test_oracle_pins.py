@@ -612,3 +612,54 @@ def test_instance_labels_invariants():
     g = np.concatenate([f[:1], 10.0 * q.feats[2:3]])
     pos = np.concatenate([scene.means[:1], q.means[2:3]])
     assert np.argmax(oracle.instance_labels(g, pos, q.feats, q.means, q.covs)[1]) == 2
+
+
+# ---------------------------------------------------------------------------
+# The linearised projected covariance of Sec. 3.2 (paper-literal reading)
+# ---------------------------------------------------------------------------
+
+def _fronto_scene(n, seed):
+    """Surfels parallel to the image plane of an unrotated camera: the
+    tangent-to-screen map is affine, so the linearisation is exact."""
+    rng = np.random.default_rng(seed)
+    cam = scenes.Camera(48, 40, 40.0, 40.0, 23.7, 19.3)
+    z = rng.uniform(2.0, 4.0, n)
+    means = np.stack([rng.uniform(-0.5, 0.5, n) * z, rng.uniform(-0.4, 0.4, n) * z, z], 1).astype(np.float32)
+    scales = rng.uniform(0.05, 0.3, (n, 2)).astype(np.float32)
+    quats = np.tile(np.array([1.0, 0.0, 0.0, 0.0], np.float32), (n, 1))
+    opacity = rng.uniform(0.3, 0.95, n).astype(np.float32)
+    return scenes.Scene(means, scales, quats, opacity, np.zeros((n, 1), np.float32)), cam
+
+
+def test_linearised_cov_fronto_parallel_closed_form():
+    """Sigma' = diag((f s_u / z)^2, (f s_v / z)^2) and mu = the pinhole image of
+    the centre for a surfel facing an unrotated camera."""
+    sc, cam = _fronto_scene(5, 0)
+    proj = oracle.project_scene(sc, cam)
+    for i in range(sc.n):
+        X, Y, Z = sc.means[i].astype(np.float64)
+        mu, S = oracle.linearised_cov(proj.T[i])
+        np.testing.assert_allclose(mu, [cam.fx * X / Z + cam.cx, cam.fy * Y / Z + cam.cy], rtol=1e-12)
+        su, sv = sc.scales[i].astype(np.float64)
+        np.testing.assert_allclose(S, np.diag([(cam.fx * su / Z) ** 2, (cam.fy * sv / Z) ** 2]), rtol=1e-12,
+                                   atol=1e-12)
+
+
+def test_linearised_tiles_equal_exact_when_affine():
+    """No tile is dropped or added where the projection is affine; the exact
+    pair count equals the oracle's tile sets."""
+    sc, cam = _fronto_scene(40, 1)
+    proj = oracle.project_scene(sc, cam)
+    st = oracle.linearised_tile_stats(proj, cam.width, cam.height, 8)
+    counts, _, _, _ = oracle.tile_sets(proj, cam.width, cam.height, 8)
+    assert st["exact_pairs"] == int(counts.sum()) > 0
+    assert st["dropped"] == 0 and st["extra"] == 0 and st["lin_pairs"] == st["exact_pairs"]
+
+
+def test_linearised_tiles_on_tilted_surfels_are_counted_consistently():
+    sc, cam = _tilted_scene(30, 7)
+    proj = oracle.project_scene(sc, cam)
+    st = oracle.linearised_tile_stats(proj, cam.width, cam.height, 8)
+    counts, _, _, _ = oracle.tile_sets(proj, cam.width, cam.height, 8)
+    assert st["exact_pairs"] == int(counts.sum())
+    assert 0 <= st["dropped"] <= st["contributions"] and st["affected"] <= cam.width * cam.height
