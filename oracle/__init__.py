@@ -4,9 +4,11 @@ TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
 CPU-baseline leg are the only callers.  The GPU library never imports, links
 or executes anything in this package, and this package shares no code with it.
 
-The arithmetic lives in ``fso.c`` (plain C, double precision, built with
-``-ffp-contract=off``); this module is argument marshalling through ctypes
-plus the finite-difference driver used to pin the analytic gradient.
+Projection, tile sets, sorting, the blend and its gradient are plain C in
+``fso.c`` (double precision, built with ``-ffp-contract=off``), called through
+ctypes.  The linearised covariance analysis, the label read-out and the
+query-guided instance labels are numpy in this file (double precision), as is
+the finite-difference driver used to pin the analytic gradient.
 
 Functions and the paper passage each follows:
   project        tangent frame, T, adj(T), cutoff, culling    Sec. 3.1 Eq. (1), Sec. 3.2 (T)

@@ -5,7 +5,7 @@
 // wave; 1 wave = 8x8 block, 4 waves = 16x16 block) of a binning tile and one
 // chunk of at most 64*CPL channels.  The tile's depth-sorted list is walked in
 // batches of BG entries:
-//   1. stage: the BG records (64 B each) are copied to LDS;
+//   1. stage: the BG records (FS_RECORD_BYTES = 96 B each) are copied to LDS;
 //   2. weights (lanes = pixels): every lane walks the batch in depth order for
 //      its pixel -- ray-splat (u, v), alpha, transmittance, the stop and Top-K
 //      tests -- and writes its blend weight w = alpha T per accepted entry to

@@ -663,3 +663,42 @@ def test_linearised_tiles_on_tilted_surfels_are_counted_consistently():
     counts, _, _, _ = oracle.tile_sets(proj, cam.width, cam.height, 8)
     assert st["exact_pairs"] == int(counts.sum())
     assert 0 <= st["dropped"] <= st["contributions"] and st["affected"] <= cam.width * cam.height
+
+
+def _pinhole_of_tangent_point(scene, i, cam, u, v):
+    """Pixel position of the tangent-plane point p + u r_u t_u + v r_v t_v
+    (Sec. 3.1 Eq. 1) through the pinhole camera, from scipy's rotation and
+    the camera's R, t, K -- no use of the oracle's T."""
+    Rq = _indep.rotation(scene.quats[i])
+    s = scene.scales[i].astype(np.float64)
+    X = scene.means[i].astype(np.float64) + u * s[0] * Rq[:, 0] + v * s[1] * Rq[:, 1]
+    pc = np.asarray(cam.R, np.float64) @ X + np.asarray(cam.t, np.float64)
+    return np.array([cam.fx * pc[0] / pc[2] + cam.cx, cam.fy * pc[1] / pc[2] + cam.cy])
+
+
+@pytest.mark.parametrize("seed", [3, 11])
+def test_linearised_cov_is_the_jacobian_of_the_perspective_projection(seed):
+    """On tilted surfels seen off-axis by a rotated camera (where T_w,1 and
+    T_w,2 are non-zero, so the mu_r T_w,c term of Sec. 3.2's linearisation
+    matters): mu is the pinhole image of the centre, and J (Sigma' = J J^T)
+    equals the central-difference Jacobian of the tangent-plane -> pixel map
+    at the tangent origin.  A wrong sign or index in the perspective term
+    moves J by O(|T_w,c| / T_w,3) relative, far above the bars."""
+    sc, cam = _tilted_scene(12, seed)
+    proj = oracle.project_scene(sc, cam)
+    h = 1e-6
+    checked = 0
+    for i in np.nonzero(proj.valid)[0]:
+        T = proj.T[i]
+        assert abs(T[2, 0]) + abs(T[2, 1]) > 1e-3 * abs(T[2, 2])   # the perspective term is present
+        mu, S = oracle.linearised_cov(T)
+        np.testing.assert_allclose(mu, _pinhole_of_tangent_point(sc, i, cam, 0.0, 0.0), rtol=1e-9, atol=1e-9)
+        J = np.zeros((2, 2))
+        for c, (du, dv) in enumerate(((h, 0.0), (0.0, h))):
+            J[:, c] = (_pinhole_of_tangent_point(sc, i, cam, du, dv) -
+                       _pinhole_of_tangent_point(sc, i, cam, -du, -dv)) / (2 * h)
+        np.testing.assert_allclose(S, J @ J.T, rtol=1e-6, atol=1e-6 * np.abs(J @ J.T).max())
+        # the ellipse axes: Sigma' (not only its trace) must match
+        np.testing.assert_allclose(np.linalg.eigvalsh(S), np.linalg.eigvalsh(J @ J.T), rtol=1e-6)
+        checked += 1
+    assert checked >= 8
