@@ -113,6 +113,10 @@ render_bwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) maxlast = max(maxlast, __shfl_xor(maxlast, d, 64));
     if (maxlast < (int)start) return;   // nothing was blended in this block
+    // a last position from another frame's lists must not walk past this
+    // tile's run into the next tile's entries
+    const uint32_t top = min((uint32_t)maxlast + 1u, end);
+    if (top <= start) return;
     double T = inside ? (double)out_T[pix] : 1.0;
     float suffix = 0.f;                 // S: sum over later contributors of w (g . c)
 
@@ -130,7 +134,6 @@ render_bwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
         }
     }
 
-    const uint32_t top = (uint32_t)maxlast + 1u;
     const uint32_t nbatch = (top - start + BG - 1) / BG;
     for (uint32_t bi = nbatch; bi-- > 0;) {
         const uint32_t b0 = start + bi * BG;

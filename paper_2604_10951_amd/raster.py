@@ -53,6 +53,7 @@ class Frame:
     keys: torch.Tensor          # sorted, first num_pairs valid
     vals: torch.Tensor
     ranges: torch.Tensor        # (total_tiles, 2)
+    generation: int = -1        # which fill of the rasterizer's shared buffers the frame read
 
     def view_image(self, rast: "Rasterizer", v: int = 0, what: str = "feat") -> torch.Tensor:
         cam = rast.cam_arr[v]
@@ -86,6 +87,10 @@ class Rasterizer:
         self.capacity = int(pair_capacity)
         self._n = -1
         self._bufs: dict[str, torch.Tensor] = {}
+        # records, pairs and ranges are shared by every frame this object
+        # renders; each preprocess refills them and bumps the generation, so a
+        # backward can tell whether its frame's lists are still the ones held
+        self.generation = 0
 
     @property
     def topk(self) -> int:
@@ -126,6 +131,7 @@ class Rasterizer:
         n = means.shape[0]
         self._ensure(n, self.capacity or max(4096, 2 * n * self.num_views))
         b = self._bufs
+        self.generation += 1
         L.check(self.lib.fs_preprocess(_p(means), _p(scales), _p(quats), _p(opacity), n, _p(self.cams_dev),
                                        self.num_views, ctypes.byref(self.opts), _p(b["records"]), _p(b["tiles"]),
                                        _p(b["tile_cache"]), _stream(self.device)), "fs_preprocess")
@@ -211,7 +217,7 @@ class Rasterizer:
         out = self.render_forward(feats, want_last=want_last, want_idx=want_idx)
         b = self._bufs
         return Frame(out["feat"], out["T"], out["n"], out["last"], out["idx"], P, b["records"], b["tiles"],
-                     b["keys"], b["vals"], b["ranges"].view(self.total_tiles, 2))
+                     b["keys"], b["vals"], b["ranges"].view(self.total_tiles, 2), self.generation)
 
     def render_nosync(self, means, scales, quats, opacity, feats, out: dict, counters=None, events=None) -> None:
         """All four stages without any host synchronisation (the pair count
@@ -225,6 +231,7 @@ class Rasterizer:
         ev = events if events is not None else [None] * 5
         if ev[0] is not None:
             ev[0].record()
+        self.generation += 1
         L.check(self.lib.fs_preprocess(_p(means), _p(scales), _p(quats), _p(opacity), n, _p(self.cams_dev),
                                        self.num_views, ctypes.byref(self.opts), _p(b["records"]), _p(b["tiles"]),
                                        _p(b["tile_cache"]), _stream(dev)), "fs_preprocess")
@@ -271,7 +278,15 @@ class Rasterizer:
         }
 
     def render_backward(self, means, scales, quats, opacity, feats, frame: Frame, grad_feat: torch.Tensor):
-        """Gradients of sum(grad_feat * frame.feat); returns a dict of tensors."""
+        """Gradients of sum(grad_feat * frame.feat); returns a dict of tensors.
+
+        The backward reads the records, sorted pairs and tile ranges this
+        rasterizer holds, so ``frame`` must be the last frame it rendered;
+        otherwise a RuntimeError is raised (render the frame again first)."""
+        if frame.generation != self.generation:
+            raise RuntimeError(f"render_backward: the frame was rendered from generation {frame.generation} of "
+                               f"this rasterizer's lists, which now hold generation {self.generation}; render it "
+                               "again before its backward")
         n, C = feats.shape
         dev = self.device
         b = self._bufs
@@ -331,6 +346,7 @@ class FrameGraph:
         torch.cuda.synchronize(rast.device)
 
     def replay(self) -> dict:
+        self.rast.generation += 1     # the replay refills the rasterizer's lists
         self.graph.replay()
         return self.out
 

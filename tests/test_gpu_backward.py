@@ -165,3 +165,31 @@ def test_segmentation_training_loop_reduces_loss():
     print("training losses", [round(x, 3) for x in losses[::5]], flush=True)
     assert all(np.isfinite(losses))
     assert losses[-1] < 0.5 * losses[0]
+
+
+@pytest.mark.parametrize("K", [0, 4])
+def test_backward_refuses_a_frame_whose_lists_were_replaced(K):
+    """Two renders (the second of a larger scene), then a backward of the
+    first: the rasterizer's shared lists now hold the second frame, so the
+    call must raise instead of differentiating the wrong lists.  The backward
+    of the latest frame still matches one from a fresh rasterizer."""
+    _case(f"stale frame guard K={K}")
+    dev = _dev()
+    scene, cam = scenes.parity_small()
+    small = scene.subset(np.arange(600))
+    rast = raster.Rasterizer(cam, device=dev, tile=8, topk=K)
+    t_small = raster.scene_tensors(small, dev)
+    t_big = raster.scene_tensors(scene, dev)
+    fr1 = rast.render(*t_small, want_last=True)
+    fr2 = rast.render(*t_big, want_last=True)
+    g1 = torch.randn_like(fr1.feat)
+    with pytest.raises(RuntimeError, match="generation"):
+        rast.render_backward(*t_small, fr1, g1)
+    g2 = torch.randn_like(fr2.feat)
+    got = rast.render_backward(*t_big, fr2, g2)
+    fresh = raster.Rasterizer(cam, device=dev, tile=8, topk=K)
+    fr3 = fresh.render(*t_big, want_last=True)
+    ref = fresh.render_backward(*t_big, fr3, g2)
+    torch.cuda.synchronize()
+    for k in got:
+        torch.testing.assert_close(got[k], ref[k], rtol=1e-4, atol=1e-6)

@@ -114,6 +114,34 @@ def test_sixteen_uneven_views_sampled_parity():
         check_image(fr, ref, rast, v, scene.channels, 8, f"view {v} ({cam.width}x{cam.height})", pixels=pix)
 
 
+def test_sixteen_views_split_schedule_as_benchmarked():
+    """The batched frame exactly as the benchmark times it: the 1M-surfel
+    scene, 16 uneven look-at views, 8x8 tiles, split Top-K render, K = 8.
+    The frame has more tiles than the sort's LDS histogram holds, so the
+    pairs go through the per-pair global count and scatter path: every
+    sorted key, value and tile range is compared bit for bit with the
+    oracle's, and sampled pixels of every view with the oracle's blend."""
+    _case("16 views, split schedule, pairs + pixels")
+    scene, cams = scenes.multiview()
+    tens = raster.scene_tensors(scene, _dev())
+    rast = raster.Rasterizer(cams, tile=8, topk=8, schedule="split", device=_dev())
+    assert rast.total_tiles > 16384
+    fr = _frame(rast, tens, want_idx=True)
+    P = check_pairs(fr, scene, cams, 8)
+    print(f"16 views: {rast.total_tiles} tiles, {P} pairs bit-exact", flush=True)
+    rng = np.random.default_rng(4)
+    for v, cam in enumerate(cams):
+        nvec = fr.view_image(rast, v, "n").reshape(-1).cpu().numpy()
+        covered = np.nonzero(nvec > 0)[0]
+        k = min(32, len(covered))
+        pix = np.unique(np.concatenate([rng.choice(covered, k, replace=False),
+                                        rng.integers(0, cam.width * cam.height, 8)]))
+        proj = oracle.project_scene(scene, cam)
+        ref = oracle.render_pixels(proj, scene.opacity, scene.feats, cam.width, pix, K=8)
+        ref.idx = np.where(ref.idx >= 0, ref.idx + v * scene.n, -1)
+        check_image(fr, ref, rast, v, scene.channels, 8, f"split view {v} ({cam.width}x{cam.height})", pixels=pix)
+
+
 def test_autotuner_picks_a_valid_config(tmp_path, monkeypatch):
     _case("autotune")
     monkeypatch.setenv("FASTSEGSIM_CACHE", str(tmp_path))
