@@ -29,7 +29,8 @@
  *   - Pointers named *_dev, and every array argument unless stated otherwise,
  *     are DEVICE memory owned by the caller.  The library never allocates,
  *     frees or keeps pointers beyond a call; scratch memory comes from the
- *     caller's `workspace` (size from fs_workspace_bytes).
+ *     caller's `workspace` (size from fs_workspace_bytes), except for
+ *     fs_bin_noalloc, whose scratch is a static device buffer of the library.
  *   - Work is enqueued on `stream` in call order.  Calls return after
  *     enqueueing; the only host synchronisation is fs_bin's optional readback
  *     of the pair count (num_pairs_host != NULL).
@@ -69,7 +70,9 @@ typedef enum fs_status {
     FS_ERR_ARG = 1,         /* invalid argument; nothing was enqueued */
     FS_ERR_CAPACITY = 2,    /* the key/value buffers are too small for the pair count */
     FS_ERR_HIP = 3,         /* a HIP launch or runtime call failed */
-    FS_ERR_UNSUPPORTED = 4  /* a valid but unimplemented option combination */
+    FS_ERR_UNSUPPORTED = 4, /* a valid but unimplemented option combination */
+    FS_ERR_SCRATCH = 5      /* the input needs more scratch than the library's static
+                               buffer holds (fs_bin_noalloc); nothing was enqueued */
 } fs_status;
 
 /* Pinhole camera, OpenCV axes (x right, y down, z forward).  A world point p
@@ -191,6 +194,29 @@ fs_status fs_bin(const float* means, const float* scales, const float* quats, co
                  const fs_camera* cams_dev, int32_t num_views, const fs_opts* opts, const uint32_t* tiles_touched,
                  const uint32_t* tile_cache, uint64_t* keys, uint32_t* vals, int64_t pair_capacity, int64_t* num_pairs_dev,
                  int64_t* num_pairs_host, void* workspace, hipStream_t stream);
+
+/*
+ * fs_bin_noalloc: fs_bin for callers that cannot allocate device memory or
+ * pass a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and errors as
+ * fs_bin, without `workspace`: the bin stage's scratch (partition totals,
+ * overflow counter and overflow queue) lives in a static device buffer of
+ * FS_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs on
+ * until the process ends.  Nothing in it has to start at zero.
+ *   - n * num_views must not exceed FS_NOALLOC_MAX_RECORDS; a larger input
+ *     returns FS_ERR_SCRATCH before anything is enqueued.
+ *   - The call allocates nothing; its first call on a device looks up that
+ *     device's buffer (the current device must be the stream's device).
+ *   - Every call on one device shares that device's buffer: calls that
+ *     overlap in time on one device (other streams, other threads) race and
+ *     must be ordered by the caller.
+ */
+#define FS_NOALLOC_MAX_RECORDS 4194304
+#define FS_NOALLOC_SCRATCH_BYTES (FS_NOALLOC_MAX_RECORDS * 8 + 65536)
+fs_status fs_bin_noalloc(const float* means, const float* scales, const float* quats, const float* opacity, int64_t n,
+                         const fs_camera* cams_dev, int32_t num_views, const fs_opts* opts,
+                         const uint32_t* tiles_touched, const uint32_t* tile_cache, uint64_t* keys, uint32_t* vals,
+                         int64_t pair_capacity, int64_t* num_pairs_dev, int64_t* num_pairs_host, hipStream_t stream);
 
 /*
  * fs_sort (Sec. 3.1: blending runs over depth-sorted surfels).  Orders the

@@ -12,7 +12,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfastsegsim.so")
 
-FS_OK, FS_ERR_ARG, FS_ERR_CAPACITY, FS_ERR_HIP, FS_ERR_UNSUPPORTED = 0, 1, 2, 3, 4
+FS_OK, FS_ERR_ARG, FS_ERR_CAPACITY, FS_ERR_HIP, FS_ERR_UNSUPPORTED, FS_ERR_SCRATCH = 0, 1, 2, 3, 4, 5
+FS_NOALLOC_MAX_RECORDS = 4194304
 FS_TILES_PRECISE, FS_TILES_BBOX = 0, 1
 FS_FEAT_F32, FS_FEAT_BF16 = 0, 1
 FS_SCHED_GRID, FS_SCHED_PERSISTENT, FS_SCHED_SPLIT = 0, 1, 2
@@ -62,6 +63,8 @@ SIGNATURES = {
     "fs_workspace_bytes": ([I64, I32, I64, I64, ctypes.POINTER(FsOpts)], ctypes.c_size_t),
     "fs_preprocess": ([P, P, P, P, I64, P, I32, ctypes.POINTER(FsOpts), P, P, P, P], I32),
     "fs_bin": ([P, P, P, P, I64, P, I32, ctypes.POINTER(FsOpts), P, P, P, P, I64, P, ctypes.POINTER(I64), P, P], I32),
+    "fs_bin_noalloc": ([P, P, P, P, I64, P, I32, ctypes.POINTER(FsOpts), P, P, P, P, I64, P, ctypes.POINTER(I64), P],
+                       I32),
     "fs_sort": ([P, P, I64, P, I64, I64, P, P, P], I32),
     "fs_render_forward": ([P, P, P, P, I32, I64, P, I32, I64, ctypes.POINTER(FsOpts), P, P, P, P, P, P, P, P], I32),
     "fs_render_labels": ([P, P, P, P, I32, I64, P, I32, I64, ctypes.POINTER(FsOpts), P, P, P, P, P, P, P], I32),

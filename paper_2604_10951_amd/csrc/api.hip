@@ -167,6 +167,41 @@ fs_status fs_bin(const float* means, const float* scales, const float* quats, co
     return p > pair_capacity ? FS_ERR_CAPACITY : FS_OK;
 }
 
+fs_status fs_bin_noalloc(const float* means, const float* scales, const float* quats, const float* opacity,
+                         int64_t n, const fs_camera* cams_dev, int32_t num_views, const fs_opts* opts,
+                         const uint32_t* tiles_touched, const uint32_t* tile_cache, uint64_t* keys, uint32_t* vals,
+                         int64_t pair_capacity, int64_t* num_pairs_dev, int64_t* num_pairs_host, hipStream_t stream) {
+    if (!valid_opts(opts) || n < 0 || num_views < 1 || !cams_dev || !num_pairs_dev || pair_capacity < 0)
+        return FS_ERR_ARG;
+    if (n > 0 && (!means || !scales || !quats || !opacity || !tiles_touched || !tile_cache)) return FS_ERR_ARG;
+    if (reinterpret_cast<uintptr_t>(tile_cache) % 16 != 0) return FS_ERR_ARG;
+    if (pair_capacity > 0 && (!keys || !vals)) return FS_ERR_ARG;
+    if (pair_capacity >= (int64_t(1) << 30)) return FS_ERR_ARG;
+    if (n * (int64_t)num_views > (int64_t)FS_NOALLOC_MAX_RECORDS) return FS_ERR_SCRATCH;
+    // the bin stage's part of the workspace layout (no sort or render regions)
+    fs_opts bin_opts = *opts;
+    bin_opts.topk = 0;
+    size_t need = 0;
+    if (!fs_workspace_layout(nullptr, n, num_views, 1, 0, &bin_opts, nullptr, &need)) return FS_ERR_ARG;
+    void* base = nullptr;
+    size_t have = 0;
+    fs_status st = hip_status(fs_noalloc_scratch(&base, &have));
+    if (st != FS_OK) return st;
+    if (need > have) return FS_ERR_SCRATCH;
+    FsWorkspace ws;
+    if (!fs_workspace_layout(base, n, num_views, 1, 0, &bin_opts, &ws, nullptr)) return FS_ERR_ARG;
+    st = hip_status(fs_launch_bin(means, scales, quats, opacity, n, cams_dev, num_views, *opts, tiles_touched,
+                                  tile_cache, keys, vals, pair_capacity, num_pairs_dev, ws, stream));
+    if (st != FS_OK || !num_pairs_host) return st;
+    int64_t p = 0;
+    st = hip_status(hipMemcpyAsync(&p, num_pairs_dev, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    if (st != FS_OK) return st;
+    st = hip_status(hipStreamSynchronize(stream));
+    if (st != FS_OK) return st;
+    *num_pairs_host = p;
+    return p > pair_capacity ? FS_ERR_CAPACITY : FS_OK;
+}
+
 fs_status fs_sort(uint64_t* keys, uint32_t* vals, int64_t pair_capacity, const int64_t* num_pairs_dev,
                   int64_t num_pairs_hint, int64_t total_tiles, uint32_t* tile_ranges, void* workspace,
                   hipStream_t stream) {
@@ -267,6 +302,7 @@ const char* fs_status_string(fs_status status) {
         case FS_ERR_CAPACITY: return "pair capacity exceeded";
         case FS_ERR_HIP: return "HIP error";
         case FS_ERR_UNSUPPORTED: return "unsupported option combination";
+        case FS_ERR_SCRATCH: return "input exceeds the static scratch buffer";
     }
     return "unknown status";
 }

@@ -10,7 +10,44 @@
 // from a base tile); the other footprints are queued and re-derived by a
 // second kernel with the same double-precision code preprocess counted them
 // with, so the emitted tiles are exactly the counted ones.
+#include <mutex>
+
 #include "fs_internal.h"
+
+// Scratch of fs_bin_noalloc: the bin stage's workspace region (partition
+// totals, overflow counter and overflow queue) for up to
+// FS_NOALLOC_MAX_RECORDS (view, surfel) records, resident on every device
+// the library runs on until the process ends.  Host code never passes this
+// name to a kernel: fs_noalloc_scratch looks up its device address.
+static __device__ __align__(256) unsigned char scratch[FS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+hipError_t fs_noalloc_scratch(void** ptr, size_t* bytes) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    *bytes = sizeof(scratch);
+    return hipSuccess;
+}
 
 namespace {
 

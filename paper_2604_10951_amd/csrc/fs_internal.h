@@ -642,6 +642,10 @@ hipError_t fs_launch_bin(const float* means, const float* scales, const float* q
                          const uint32_t* tile_cache, uint64_t* keys, uint32_t* vals, int64_t capacity,
                          int64_t* num_pairs, const FsWorkspace& ws, hipStream_t s);
 
+// Device address and size of the static scratch of fs_bin_noalloc on the
+// current device (bin.hip).
+hipError_t fs_noalloc_scratch(void** ptr, size_t* bytes);
+
 hipError_t fs_launch_sort(uint64_t* keys, uint32_t* vals, int64_t capacity, const int64_t* num_pairs, int64_t hint,
                           int64_t total_tiles, uint32_t* ranges, const FsWorkspace& ws, hipStream_t s);
 
