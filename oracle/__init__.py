@@ -13,13 +13,19 @@ the finite-difference driver used to pin the analytic gradient.
 Functions and the paper passage each follows:
   project        tangent frame, T, adj(T), cutoff, culling    Sec. 3.1 Eq. (1), Sec. 3.2 (T)
   tile_sets      per-pixel footprint test -> tiles            Sec. 3.2 (exact result of the
-                                                               precise tile intersection)
+                                                               precise tile intersection; or the
+                                                               linearised Sigma' ellipse, read
+                                                               literally; optional low-pass disc)
   linearised_cov / linearised_tile_stats
                  the linearised projected covariance Sigma' and what tiles it misses
                                                                Sec. 3.2 (the printed formula, read literally)
   sort_pairs     (tile, depth) ordering                        Sec. 3.1 (depth-sorted surfels)
   render_image / render_pixels
                  front-to-back blend, full or Top-K            Sec. 3.1 Eq. (2), Sec. 3.4 F_TopK
+  render_lists / render_tiled
+                 the same blend walking each pixel's tile list  Sec. 3.1 Eq. (2) over the tile lists of
+                                                               Sec. 3.2; depth and normal outputs
+  normals        n = t_u x t_v in camera space, facing it     Sec. 3.1
   labels         per-pixel argmax channel of a render          Sec. 3.3, Sec. 3.5 (masks from blended
                                                                class / instance channels)
   query_density_ratio / instance_labels
@@ -79,12 +85,16 @@ def load():
     lib.fso_surfel_d2_image.argtypes = [_d, I32, I32, _d]
     lib.fso_conic_bounds.argtypes = [_d, D, _d]
     lib.fso_conic_bounds.restype = I32
-    lib.fso_tile_sets.argtypes = [_i32, _u32, _d, _d, I64, I32, I32, I32, I32, I64, I64, _u32, _i8, _u64, _u32]
+    lib.fso_tile_sets.argtypes = [_i32, _u32, _d, _d, _d, I64, I32, I32, I32, I32, I32, I32, I64, I64, _u32, _i8,
+                                  _u64, _u32]
     lib.fso_tile_sets.restype = I64
     lib.fso_sort_pairs.argtypes = [_u64, _u32, I64]
     lib.fso_tile_ranges.argtypes = [_u64, I64, I64, _u32]
-    lib.fso_render_pixels.argtypes = [_i32, _u32, _d, _d, _d, _d, I64, I32, I32, _i64, I64, D, D, D, I32, I32,
-                                      _d, _d, _d, _i32, _i32, _i32, _i32]
+    lib.fso_render_pixels.argtypes = [_i32, _u32, _d, _d, _d, _d, _d, _d, I64, I32, I32, _i64, I64, I32, D, D, D,
+                                      I32, I32, _d, _d, _d, _i32, _i32, _i32, _i32, _d]
+    lib.fso_render_lists.argtypes = [_i32, _u32, _d, _d, _d, _d, _d, _d, I64, I32, I32, I32, I32, _u32, _u32, _i64,
+                                     I64, I32, D, D, D, I32, I32, _d, _d, _d, _i32, _i32, _i32, _i32, _d]
+    lib.fso_normals.argtypes = [_d, _d, I64, _d, _d]
     lib.fso_render_image.argtypes = [_i32, _u32, _d, _d, _d, _d, I64, I32, I32, I32, I32, D, D, D, I32, I32,
                                      _d, _d, _d, _i32, _i32, _i32, _i32]
     lib.fso_render_grad.argtypes = [_d, _d, _d, _d, _d, I64, I32, _d, I32, D, D, D, I32, _d, _d, _d, _d, _d, _d,
@@ -149,10 +159,18 @@ def conic_bounds(H: np.ndarray, k2: float):
     return bb if ok else None
 
 
+MODES = {"precise": 0, "linearised": 2}
+
+
 def tile_sets(proj: Projection, width: int, height: int, tile: int, *, prefilter: bool = True,
-              tile_offset: int = 0, val_offset: int = 0, pairs: bool = False):
+              tile_offset: int = 0, val_offset: int = 0, pairs: bool = False, mode: str = "precise",
+              lowpass: bool = False):
     """Per-surfel tile counts (and optionally the unsorted pair list).
 
+    mode "precise": a tile holds a surfel iff one of its pixel centres is in
+    the exact footprint u^2 + v^2 <= k^2; "linearised": iff one is in the
+    linearised ellipse of Sec. 3.2; lowpass adds the low-pass disc
+    2 |x - mu|^2 <= k^2.
     Returns (counts uint32 (N,), flags int8 (N,), keys uint64 (P,), vals uint32 (P,)).
     """
     lib = load()
@@ -160,18 +178,20 @@ def tile_sets(proj: Projection, width: int, height: int, tile: int, *, prefilter
     counts = np.zeros(n, np.uint32)
     flags = np.zeros(n, np.int8)
     H = _f64(proj.H)
-    total = lib.fso_tile_sets(_ptr(proj.valid, _i32), _ptr(proj.zkey, _u32), _ptr(H, _d), _ptr(proj.k2, _d), n,
-                              width, height, tile, int(prefilter), tile_offset, val_offset, _ptr(counts, _u32),
-                              _ptr(flags, _i8), None, None)
+    T = _f64(proj.T)
+    md = MODES[mode]
+    total = lib.fso_tile_sets(_ptr(proj.valid, _i32), _ptr(proj.zkey, _u32), _ptr(T, _d), _ptr(H, _d),
+                              _ptr(proj.k2, _d), n, width, height, tile, int(prefilter), md, int(lowpass),
+                              tile_offset, val_offset, _ptr(counts, _u32), _ptr(flags, _i8), None, None)
     if total < 0:
         raise MemoryError("oracle tile_sets failed")
     keys = vals = None
     if pairs:
         keys = np.zeros(max(total, 1), np.uint64)
         vals = np.zeros(max(total, 1), np.uint32)
-        lib.fso_tile_sets(_ptr(proj.valid, _i32), _ptr(proj.zkey, _u32), _ptr(H, _d), _ptr(proj.k2, _d), n,
-                          width, height, tile, int(prefilter), tile_offset, val_offset, _ptr(counts, _u32),
-                          _ptr(flags, _i8), _ptr(keys, _u64), _ptr(vals, _u32))
+        lib.fso_tile_sets(_ptr(proj.valid, _i32), _ptr(proj.zkey, _u32), _ptr(T, _d), _ptr(H, _d),
+                          _ptr(proj.k2, _d), n, width, height, tile, int(prefilter), md, int(lowpass), tile_offset,
+                          val_offset, _ptr(counts, _u32), _ptr(flags, _i8), _ptr(keys, _u64), _ptr(vals, _u32))
         keys, vals = keys[:total], vals[:total]
     return counts, flags, keys, vals
 
@@ -237,7 +257,8 @@ def tile_ranges(keys: np.ndarray, num_tiles: int) -> np.ndarray:
     return ranges
 
 
-def sorted_pairs(scene, cams, tile: int, alpha_min: float = ALPHA_MIN, prefilter: bool = True):
+def sorted_pairs(scene, cams, tile: int, alpha_min: float = ALPHA_MIN, prefilter: bool = True,
+                 mode: str = "precise", lowpass: bool = False):
     """Sorted (key, value) list over one or more views, tile ids offset per view
     in view order and values = view * N + surfel index."""
     cams = cams if isinstance(cams, (list, tuple)) else [cams]
@@ -246,7 +267,7 @@ def sorted_pairs(scene, cams, tile: int, alpha_min: float = ALPHA_MIN, prefilter
     for v, cam in enumerate(cams):
         proj = project_scene(scene, cam, alpha_min)
         _, _, k, val = tile_sets(proj, cam.width, cam.height, tile, prefilter=prefilter, tile_offset=tile_off,
-                                 val_offset=v * n, pairs=True)
+                                 val_offset=v * n, pairs=True, mode=mode, lowpass=lowpass)
         ks.append(k)
         vs.append(val)
         tile_off += ((cam.width + tile - 1) // tile) * ((cam.height + tile - 1) // tile)
@@ -263,6 +284,29 @@ class Render:
     idx: np.ndarray      # (..., kcap) blended surfel indices front to back, -1 padded
     amb: np.ndarray      # (...)   1 if a threshold decision lies within 1e-5 relative
     nclamp: np.ndarray   # (...)   how many contributors hit alpha_max
+    D: np.ndarray | None = None      # (...)   blended depth sum_i w_i z_i(x) of the intersection points
+    absD: np.ndarray | None = None   # (...)   sum_i w_i |z_i|
+    N: np.ndarray | None = None      # (..., 3) blended camera-space normal sum_i w_i n_i
+    absN: np.ndarray | None = None   # (..., 3) sum_i w_i |n_i|
+
+
+def _with_geo(r: "Render", geo, shape):
+    if geo is not None:
+        g = geo.reshape(shape + (8,))
+        r.D, r.absD, r.N, r.absN = g[..., 0], g[..., 1], g[..., 2:5], g[..., 5:8]
+    return r
+
+
+def normals(means, quats, cam) -> np.ndarray:
+    """Camera-space unit normals n = R (t_u x t_v) of the surfels (Sec. 3.1),
+    flipped to face the camera; (N, 3)."""
+    lib = load()
+    means, quats = _f64(means), _f64(quats)
+    n = means.shape[0]
+    out = np.zeros((n, 3))
+    ca = camera_array(cam)
+    lib.fso_normals(_ptr(means, _d), _ptr(quats, _d), n, _ptr(ca, _d), _ptr(out, _d))
+    return out
 
 
 def _render_common(proj, feats, opacity):
@@ -299,8 +343,10 @@ def render_image(proj: Projection, opacity, feats, width: int, height: int, *, K
 
 def render_pixels(proj: Projection, opacity, feats, width: int, pix, *, K: int = 0, kcap: int | None = None,
                   alpha_min: float = ALPHA_MIN, alpha_max: float = ALPHA_MAX, t_stop: float = T_STOP,
-                  by_weight: bool = False) -> Render:
-    """Brute-force render of selected pixels (pix = py * width + px)."""
+                  by_weight: bool = False, lowpass: bool = False, normals=None) -> Render:
+    """Brute-force render of selected pixels (pix = py * width + px): every
+    valid surfel is a candidate.  With normals ((N, 3) camera-space surfel
+    normals) the depth and normal outputs are filled too."""
     lib = load()
     feats, opacity, H = _render_common(proj, feats, opacity)
     n, C = feats.shape
@@ -314,11 +360,73 @@ def render_pixels(proj: Projection, opacity, feats, width: int, pix, *, K: int =
     idx = np.zeros((m, max(kcap, 1)), np.int32)
     amb = np.zeros(m, np.int32)
     ncl = np.zeros(m, np.int32)
-    lib.fso_render_pixels(_ptr(proj.valid, _i32), _ptr(proj.zkey, _u32), _ptr(H, _d), _ptr(proj.k2, _d),
-                          _ptr(opacity, _d), _ptr(feats, _d), n, C, width, _ptr(pix, _i64), m, alpha_min, alpha_max,
-                          t_stop, -K if by_weight else K, kcap, _ptr(F, _d), _ptr(absF, _d), _ptr(T, _d), _ptr(nout, _i32),
-                          _ptr(idx, _i32), _ptr(amb, _i32), _ptr(ncl, _i32))
-    return Render(F, absF, T, nout, idx[:, :kcap], amb, ncl)
+    Tm = _f64(proj.T)
+    nrm = None if normals is None else _f64(normals)
+    geo = None if normals is None else np.zeros((m, 8))
+    lib.fso_render_pixels(_ptr(proj.valid, _i32), _ptr(proj.zkey, _u32), _ptr(Tm, _d), _ptr(H, _d),
+                          _ptr(proj.k2, _d), _ptr(opacity, _d), _ptr(feats, _d),
+                          None if nrm is None else _ptr(nrm, _d), n, C, width, _ptr(pix, _i64), m, int(lowpass),
+                          alpha_min, alpha_max, t_stop, -K if by_weight else K, kcap, _ptr(F, _d), _ptr(absF, _d),
+                          _ptr(T, _d), _ptr(nout, _i32), _ptr(idx, _i32), _ptr(amb, _i32), _ptr(ncl, _i32),
+                          None if geo is None else _ptr(geo, _d))
+    return _with_geo(Render(F, absF, T, nout, idx[:, :kcap], amb, ncl), geo, (m,))
+
+
+def render_lists(proj: Projection, opacity, feats, width: int, height: int, tile: int, vals, ranges, *, pix=None,
+                 K: int = 0, kcap: int | None = None, alpha_min: float = ALPHA_MIN, alpha_max: float = ALPHA_MAX,
+                 t_stop: float = T_STOP, by_weight: bool = False, lowpass: bool = False, normals=None) -> Render:
+    """Render from sorted tile lists (one view, tile ids from 0, values =
+    surfel indices): every pixel walks its tile's list front to back.  pix =
+    None renders the whole image (outputs shaped (height, width, ...)),
+    otherwise the listed pixels py * width + px."""
+    lib = load()
+    feats, opacity, H = _render_common(proj, feats, opacity)
+    n, C = feats.shape
+    kcap = int(kcap if kcap is not None else (K if K > 0 else 64))
+    vals = np.ascontiguousarray(vals, np.uint32)
+    ranges = np.ascontiguousarray(ranges, np.uint32).reshape(-1)
+    pixa = None if pix is None else np.ascontiguousarray(pix, np.int64)
+    m = width * height if pixa is None else pixa.shape[0]
+    F = np.zeros((m, C))
+    absF = np.zeros((m, C))
+    T = np.zeros(m)
+    nout = np.zeros(m, np.int32)
+    idx = np.zeros((m, max(kcap, 1)), np.int32)
+    amb = np.zeros(m, np.int32)
+    ncl = np.zeros(m, np.int32)
+    Tm = _f64(proj.T)
+    nrm = None if normals is None else _f64(normals)
+    geo = None if normals is None else np.zeros((m, 8))
+    rc = lib.fso_render_lists(_ptr(proj.valid, _i32), _ptr(proj.zkey, _u32), _ptr(Tm, _d), _ptr(H, _d),
+                              _ptr(proj.k2, _d), _ptr(opacity, _d), _ptr(feats, _d),
+                              None if nrm is None else _ptr(nrm, _d), n, C, width, height, tile,
+                              _ptr(vals, _u32), _ptr(ranges, _u32), None if pixa is None else _ptr(pixa, _i64), m,
+                              int(lowpass), alpha_min, alpha_max, t_stop, -K if by_weight else K, kcap, _ptr(F, _d),
+                              _ptr(absF, _d), _ptr(T, _d), _ptr(nout, _i32), _ptr(idx, _i32), _ptr(amb, _i32),
+                              _ptr(ncl, _i32), None if geo is None else _ptr(geo, _d))
+    if rc != 0:
+        raise ValueError("render_lists: a list names an invalid surfel")
+    sh = (height, width) if pixa is None else (m,)
+    r = Render(F.reshape(sh + (C,)), absF.reshape(sh + (C,)), T.reshape(sh), nout.reshape(sh),
+               idx.reshape(sh + (max(kcap, 1),))[..., :kcap], amb.reshape(sh), ncl.reshape(sh))
+    return _with_geo(r, geo, sh)
+
+
+def render_tiled(scene, cam, tile: int, *, mode: str = "precise", lowpass: bool = False, K: int = 0,
+                 kcap: int | None = None, pix=None, geometry: bool = False, by_weight: bool = False,
+                 alpha_min: float = ALPHA_MIN, alpha_max: float = ALPHA_MAX, t_stop: float = T_STOP) -> Render:
+    """One view through the whole tiled definition: projection, tile sets of
+    the given assignment mode (and low-pass option), sorted pairs, tile
+    ranges, then render_lists (with depth and normal outputs if geometry)."""
+    proj = project_scene(scene, cam, alpha_min)
+    _, _, keys, vals = tile_sets(proj, cam.width, cam.height, tile, pairs=True, mode=mode, lowpass=lowpass)
+    keys, vals = sort_pairs(keys, vals)
+    ntiles = ((cam.width + tile - 1) // tile) * ((cam.height + tile - 1) // tile)
+    ranges = tile_ranges(keys, ntiles)
+    nrm = normals(scene.means, scene.quats, cam) if geometry else None
+    return render_lists(proj, scene.opacity, scene.feats, cam.width, cam.height, tile, vals, ranges, pix=pix, K=K,
+                        kcap=kcap, alpha_min=alpha_min, alpha_max=alpha_max, t_stop=t_stop, by_weight=by_weight,
+                        lowpass=lowpass, normals=nrm)
 
 
 def render_scene(scene, cam, *, K: int = 0, kcap: int | None = None, alpha_min: float = ALPHA_MIN,

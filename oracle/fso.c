@@ -35,6 +35,19 @@
  *     intersection must reach)                         Sec. 3.2
  *   - the gradient of L = sum_p g_p . F_p by the chain rule (no paper
  *     passage: the paper trains through the renderer, Sec. 3.5)
+ *   - the paper-literal tile assignment: the linearised projected covariance
+ *     Sigma' of Sec. 3.2, read as J J^T with J the Jacobian of the perspective
+ *     map at the tangent origin; a tile holds a surfel iff some pixel centre
+ *     of the tile lies in (x - mu)^T Sigma'^-1 (x - mu) <= k^2
+ *                                                      Sec. 3.2
+ *   - pixel depth and normal outputs: blended depth of the ray-splat
+ *     intersection point and blended surfel normal n = t_u x t_v (in camera
+ *     space, facing the camera)                        Sec. 3.1, Eq. (2)
+ *   - the 2D Gaussian splatting screen-space low-pass option: the response
+ *     exp(-min(u^2 + v^2, 2 |x - mu|^2) / 2), mu the projected centre
+ *     (a screen Gaussian of variance 1/2 px^2 that keeps sub-pixel surfels
+ *     visible; not part of the paper, an option of the 2DGS renderer it
+ *     builds on)
  */
 #include <math.h>
 #include <stdint.h>
@@ -237,6 +250,74 @@ static int pixel_range(const double H[9], double k2, int W, int Hh, int prefilte
     return r[0] <= r[1] && r[2] <= r[3];
 }
 
+/* The projected centre mu = (T1 . e3, T2 . e3) / (Tw . e3), e3 = (0, 0, 1):
+ * the image of the tangent origin under x' = T u (Sec. 3.2). */
+static void projected_centre(const double T[9], double mu[2])
+{
+    mu[0] = T[2] / T[8];
+    mu[1] = T[5] / T[8];
+}
+
+/*
+ * The linearised projected covariance of Sec. 3.2.  The printed formula is
+ * garbled; it is read as the local linearisation of the perspective map
+ * x(u, v) = (T1 . (u, v, 1), T2 . (u, v, 1)) / (Tw . (u, v, 1)) at the tangent
+ * origin: J_rc = (T_rc - mu_r T_wc) / T_w3 (r, c in {1, 2}) and Sigma' = J J^T
+ * (the tangent coordinates have unit variance; the scales are inside T).
+ * Outputs mu, Sigma' = (S00, S01, S11) and its inverse P = (P00, P01, P11).
+ * Returns 0 if Sigma' is not positive definite in floating point.
+ */
+static int linearised_ellipse(const double T[9], double mu[2], double Sg[3], double P[3])
+{
+    projected_centre(T, mu);
+    const double J00 = (T[0] - mu[0] * T[6]) / T[8];
+    const double J01 = (T[1] - mu[0] * T[7]) / T[8];
+    const double J10 = (T[3] - mu[1] * T[6]) / T[8];
+    const double J11 = (T[4] - mu[1] * T[7]) / T[8];
+    Sg[0] = J00 * J00 + J01 * J01;
+    Sg[1] = J00 * J10 + J01 * J11;
+    Sg[2] = J10 * J10 + J11 * J11;
+    const double det = Sg[0] * Sg[2] - Sg[1] * Sg[1];
+    if (!(det > 0.0) || !isfinite(det)) return 0;
+    P[0] = Sg[2] / det;
+    P[1] = -Sg[1] / det;
+    P[2] = Sg[0] / det;
+    return 1;
+}
+
+/* Mahalanobis distance (x - mu)^T Sigma'^-1 (x - mu) of point (x, y). */
+static double linearised_q(const double mu[2], const double P[3], double x, double y)
+{
+    const double dx = x - mu[0], dy = y - mu[1];
+    return (P[0] * dx * dx + 2.0 * P[1] * dx * dy) + P[2] * dy * dy;
+}
+
+/* Screen-space term of the low-pass option: 2 |x - mu|^2, i.e. the squared
+ * distance to the projected centre in units of a standard deviation of
+ * sqrt(1/2) px. */
+static double lowpass_r2(const double mu[2], double x, double y)
+{
+    const double dx = x - mu[0], dy = y - mu[1];
+    return 2.0 * (dx * dx + dy * dy);
+}
+
+/* Camera depth of the ray-splat intersection point p_c + u U + v V: its third
+ * coordinate, Tw . (u, v, 1) (Tw = (U_z, V_z, p_c,z), the last row of T). */
+static double intersection_depth(const double T[9], double u, double v)
+{
+    return (T[6] * u + T[7] * v) + T[8];
+}
+
+/* Pixel index range [lo, hi] of pixel centres with a continuous coordinate in
+ * [c0, c1], widened by one pixel. */
+static void centre_range(double c0, double c1, double lim, int* lo, int* hi)
+{
+    c0 = c0 < -lim ? -lim : (c0 > lim ? lim : c0);
+    c1 = c1 < -lim ? -lim : (c1 > lim ? lim : c1);
+    *lo = (int)ceil(c0 - 0.5) - 1;
+    *hi = (int)floor(c1 - 0.5) + 1;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Exported: projection                                                      */
 /* ------------------------------------------------------------------------ */
@@ -280,18 +361,99 @@ int fso_surfel_d2_image(const double* H, int W, int Hh, double* out)
 /* Pixel-centre bounds of the screen conic (x0, x1, y0, y1), 0 if none. */
 int fso_conic_bounds(const double* H, double k2, double* bb) { return conic_bounds(H, k2, bb); }
 
+/* Assignment modes of fso_tile_sets (the values of the library's tile modes). */
+enum { ASSIGN_EXACT = 0, ASSIGN_LINEARISED = 2 };
+
+/* Candidate pixel range of surfel i for a tile assignment: the union of the
+ * closed-form bounds of every shape the assignment tests (the exact conic, or
+ * the linearised ellipse, plus the low-pass disc), each widened by one pixel;
+ * the whole image if prefilter == 0 or a shape is unbounded. */
+static int assign_range(const double T[9], const double H[9], double k2, int mode, int lowpass, int W, int Hh,
+                        int prefilter, int r[4])
+{
+    r[0] = 0;
+    r[1] = W - 1;
+    r[2] = 0;
+    r[3] = Hh - 1;
+    if (!prefilter) return 1;
+    const double lim = 4.0 * (double)(W > Hh ? W : Hh) + 8.0;
+    int lo[2] = {1 << 30, 1 << 30}, hi[2] = {-(1 << 30), -(1 << 30)};
+    double bb[4];
+    if (mode == ASSIGN_LINEARISED) {
+        double mu[2], Sg[3], P[3];
+        if (!linearised_ellipse(T, mu, Sg, P)) return 1;
+        const double k = sqrt(k2);
+        bb[0] = mu[0] - k * sqrt(Sg[0]);
+        bb[1] = mu[0] + k * sqrt(Sg[0]);
+        bb[2] = mu[1] - k * sqrt(Sg[2]);
+        bb[3] = mu[1] + k * sqrt(Sg[2]);
+        if (!all_finite(bb, 4)) return 1;
+    } else if (!conic_bounds(H, k2, bb)) {
+        return 1;
+    }
+    for (int a = 0; a < 2; ++a) {
+        int l, h;
+        centre_range(bb[2 * a], bb[2 * a + 1], lim, &l, &h);
+        lo[a] = l < lo[a] ? l : lo[a];
+        hi[a] = h > hi[a] ? h : hi[a];
+    }
+    if (lowpass) {
+        double mu[2];
+        projected_centre(T, mu);
+        const double rd = sqrt(0.5 * k2);
+        if (!isfinite(mu[0]) || !isfinite(mu[1])) return 1;
+        for (int a = 0; a < 2; ++a) {
+            int l, h;
+            centre_range(mu[a] - rd, mu[a] + rd, lim, &l, &h);
+            lo[a] = l < lo[a] ? l : lo[a];
+            hi[a] = h > hi[a] ? h : hi[a];
+        }
+    }
+    if (lo[0] > r[0]) r[0] = lo[0];
+    if (hi[0] < r[1]) r[1] = hi[0];
+    if (lo[1] > r[2]) r[2] = lo[1];
+    if (hi[1] < r[3]) r[3] = hi[1];
+    return r[0] <= r[1] && r[2] <= r[3];
+}
+
+/* Does pixel centre (x, y) assign surfel i to its tile?  exact: u^2 + v^2 <=
+ * k2; linearised: the Sec. 3.2 ellipse; with lowpass, also 2 |x - mu|^2 <= k2.
+ * *near = 1 if a decision taken lies within 1e-12 relative of k2. */
+static int assigns(const double T[9], const double H[9], double k2, int mode, int lowpass, int lin_ok,
+                   const double mu[2], const double P[3], double x, double y, int* near)
+{
+    double q;
+    if (mode == ASSIGN_LINEARISED) {
+        q = lin_ok ? linearised_q(mu, P, x, y) : INFINITY;
+    } else {
+        double u, v;
+        q = pixel_d2(H, x, y, &u, &v);
+    }
+    if (fabs(q - k2) < 1e-12 * k2) *near = 1;
+    int in = q <= k2;
+    if (lowpass) {
+        const double r2 = lowpass_r2(mu, x, y);
+        if (fabs(r2 - k2) < 1e-12 * k2) *near = 1;
+        in = in || r2 <= k2;
+    }
+    return in;
+}
+
 /*
  * Tile sets by the per-pixel definition: tile (tx, ty) holds surfel i iff some
- * pixel centre in the tile has u^2 + v^2 <= k2.  counts[i] = number of tiles.
- * If keys != NULL, pairs are written (in surfel order, tiles row-major) at
- * offsets[i] (exclusive prefix of counts, computed here serially):
+ * pixel centre in the tile assigns it (assigns() above: the exact footprint
+ * u^2 + v^2 <= k2 for mode ASSIGN_EXACT, the linearised ellipse of Sec. 3.2
+ * for ASSIGN_LINEARISED, and with lowpass != 0 also the low-pass disc).
+ * counts[i] = number of tiles.  If keys != NULL, pairs are written (in surfel
+ * order, tiles row-major) at offsets[i] (exclusive prefix of counts, computed
+ * here serially):
  *   key = ((tile_offset + ty * tiles_x + tx) << 32) | zkey[i],  value = val_offset + i.
- * flag[i] = 1 if any pixel test of surfel i had relative margin
- * |d2 - k2| / k2 below 1e-12 (a decision floating point could flip).
+ * flag[i] = 1 if any pixel test of surfel i had relative margin below 1e-12
+ * (a decision floating point could flip).
  */
-int64_t fso_tile_sets(const int32_t* valid, const uint32_t* zkey, const double* H, const double* k2, int64_t n, int W,
-                      int Hh, int S, int prefilter, int64_t tile_offset, int64_t val_offset, uint32_t* counts,
-                      int8_t* flag, uint64_t* keys, uint32_t* vals)
+int64_t fso_tile_sets(const int32_t* valid, const uint32_t* zkey, const double* T, const double* H, const double* k2,
+                      int64_t n, int W, int Hh, int S, int prefilter, int mode, int lowpass, int64_t tile_offset,
+                      int64_t val_offset, uint32_t* counts, int8_t* flag, uint64_t* keys, uint32_t* vals)
 {
     const int tx_n = (W + S - 1) / S, ty_n = (Hh + S - 1) / S;
     int nthreads = 1;
@@ -319,17 +481,22 @@ int64_t fso_tile_sets(const int32_t* valid, const uint32_t* zkey, const double* 
                 flag[i] = 0;
             }
             if (!valid[i]) continue;
+            const double* Ti = T + 9 * i;
+            const double* Hi = H + 9 * i;
             int r[4];
-            if (!pixel_range(H + 9 * i, k2[i], W, Hh, prefilter, r)) continue;
+            if (!assign_range(Ti, Hi, k2[i], mode, lowpass, W, Hh, prefilter, r)) continue;
+            double mu[2], Sg[3], P[3] = {0.0, 0.0, 0.0};
+            int lin_ok = 0;
+            if (mode == ASSIGN_LINEARISED)
+                lin_ok = linearised_ellipse(Ti, mu, Sg, P);
+            else
+                projected_centre(Ti, mu);
             uint32_t cnt = 0;
-            int8_t fl = 0;
+            int fl = 0;
             for (int py = r[2]; py <= r[3]; ++py)
-                for (int px = r[0]; px <= r[1]; ++px) {
-                    double u, v;
-                    const double d2 = pixel_d2(H + 9 * i, px + 0.5, py + 0.5, &u, &v);
-                    if (fabs(d2 - k2[i]) < 1e-12 * k2[i]) fl = 1;
-                    if (d2 <= k2[i]) mk[(py / S) * tx_n + px / S] = 1;
-                }
+                for (int px = r[0]; px <= r[1]; ++px)
+                    if (assigns(Ti, Hi, k2[i], mode, lowpass, lin_ok, mu, P, px + 0.5, py + 0.5, &fl))
+                        mk[(py / S) * tx_n + px / S] = 1;
             int64_t o = pass == 1 ? offsets[i] : 0;
             for (int ty = r[2] / S; ty <= r[3] / S; ++ty)
                 for (int tx = r[0] / S; tx <= r[1] / S; ++tx) {
@@ -346,7 +513,7 @@ int64_t fso_tile_sets(const int32_t* valid, const uint32_t* zkey, const double* 
                 }
             if (pass == 0) {
                 counts[i] = cnt;
-                flag[i] = fl;
+                flag[i] = (int8_t)fl;
             }
         }
         free(offsets);
@@ -409,8 +576,13 @@ int fso_tile_ranges(const uint64_t* keys, int64_t m, int64_t num_tiles, uint32_t
 typedef struct {
     uint32_t zkey;
     uint32_t idx;
-    double d2;
+    double d2;   /* u^2 + v^2 (with the low-pass option: min(u^2 + v^2, 2 |x - mu|^2)) */
+    double z;    /* camera depth of the ray-splat intersection point (0 if not needed) */
 } cand_t;
+
+/* Per-pixel geometry outputs of a blend: GEO_LEN doubles per pixel,
+ * [depth, |depth| term sum, normal xyz, |normal| term sums xyz]. */
+enum { GEO_LEN = 8 };
 
 static int cand_cmp(const void* a, const void* b)
 {
@@ -429,7 +601,20 @@ typedef struct {
 
 static int blend_pixel_by_weight(const cand_t* cs, int64_t m, const double* k2, const double* opacity,
                                  const double* feats, int C, int K, const blend_opts* bo, double* F, double* absF,
-                                 double* Tout, int32_t* idx, int32_t* amb, int32_t* nclamp, int32_t* last_cand);
+                                 double* Tout, int32_t* idx, int32_t* amb, int32_t* nclamp, int32_t* last_cand,
+                                 const double* normals, double* geo);
+
+/* Adds one contributor (weight w, intersection depth z, normal nrm) to a
+ * pixel's geometry outputs. */
+static void geo_add(double* geo, double w, double z, const double* nrm)
+{
+    geo[0] += w * z;
+    geo[1] += w * fabs(z);
+    for (int k = 0; k < 3; ++k) {
+        geo[2 + k] += w * nrm[k];
+        geo[5 + k] += w * fabs(nrm[k]);
+    }
+}
 
 /*
  * Front-to-back blend of one pixel over its candidates sorted by depth key
@@ -443,11 +628,13 @@ static int blend_pixel_by_weight(const cand_t* cs, int64_t m, const double* k2, 
  */
 static int blend_pixel(const cand_t* cs, int64_t m, const double* k2, const double* opacity, const double* feats,
                        int C, const blend_opts* bo, double* F, double* absF, double* Tout, int32_t* idx,
-                       int32_t* amb, int32_t* nclamp, int32_t* last_cand)
+                       int32_t* amb, int32_t* nclamp, int32_t* last_cand, const double* normals, double* geo)
 {
+    if (geo)
+        for (int k = 0; k < GEO_LEN; ++k) geo[k] = 0.0;
     if (bo->K < 0)
         return blend_pixel_by_weight(cs, m, k2, opacity, feats, C, -bo->K, bo, F, absF, Tout, idx, amb, nclamp,
-                                     last_cand);
+                                     last_cand, normals, geo);
     double T = 1.0;
     int n = 0, a = 0, ncl = 0;
     int32_t lastc = -1;
@@ -473,6 +660,7 @@ static int blend_pixel(const cand_t* cs, int64_t m, const double* k2, const doub
             F[ch] += w * c[ch];
             absF[ch] += w * fabs(c[ch]);
         }
+        if (geo) geo_add(geo, w, cs[j].z, normals + 3 * (int64_t)i);
         T = Tn;
         if (n < bo->kcap) idx[n] = (int32_t)i;
         ++n;
@@ -517,7 +705,8 @@ static int position_cmp(const void* a, const void* b)
  */
 static int blend_pixel_by_weight(const cand_t* cs, int64_t m, const double* k2, const double* opacity,
                                  const double* feats, int C, int K, const blend_opts* bo, double* F, double* absF,
-                                 double* Tout, int32_t* idx, int32_t* amb, int32_t* nclamp, int32_t* last_cand)
+                                 double* Tout, int32_t* idx, int32_t* amb, int32_t* nclamp, int32_t* last_cand,
+                                 const double* normals, double* geo)
 {
     double T = 1.0;
     int a = 0, ncl = 0;
@@ -556,6 +745,7 @@ static int blend_pixel_by_weight(const cand_t* cs, int64_t m, const double* k2, 
             F[ch] += ws[s].w * c[ch];
             absF[ch] += ws[s].w * fabs(c[ch]);
         }
+        if (geo) geo_add(geo, ws[s].w, cs[ws[s].j].z, normals + 3 * (int64_t)ws[s].i);
         if (s < bo->kcap) idx[s] = (int32_t)ws[s].i;
     }
     free(ws);
@@ -577,10 +767,11 @@ static int is_candidate(double d2, double k2) { return d2 <= k2 * (1.0 + AMBIG_R
  * w |c|, the scale of the rounding error of F), T_final, n, idx (kcap, -1
  * padded), amb, nclamp.
  */
-int fso_render_pixels(const int32_t* valid, const uint32_t* zkey, const double* H, const double* k2,
-                      const double* opacity, const double* feats, int64_t n, int C, int W, const int64_t* pix,
-                      int64_t npix, double alpha_min, double alpha_max, double t_stop, int K, int kcap, double* F,
-                      double* absF, double* Tout, int32_t* nout, int32_t* idx, int32_t* amb, int32_t* nclamp)
+int fso_render_pixels(const int32_t* valid, const uint32_t* zkey, const double* T, const double* H, const double* k2,
+                      const double* opacity, const double* feats, const double* normals, int64_t n, int C, int W,
+                      const int64_t* pix, int64_t npix, int lowpass, double alpha_min, double alpha_max,
+                      double t_stop, int K, int kcap, double* F, double* absF, double* Tout, int32_t* nout,
+                      int32_t* idx, int32_t* amb, int32_t* nclamp, double* geo)
 {
     (void)alpha_min;
     blend_opts bo = {alpha_min, alpha_max, t_stop, K, kcap};
@@ -596,7 +787,13 @@ int fso_render_pixels(const int32_t* valid, const uint32_t* zkey, const double* 
             for (int64_t i = 0; i < n; ++i) {
                 if (!valid[i]) continue;
                 double u, v;
-                const double d2 = pixel_d2(H + 9 * i, x, y, &u, &v);
+                double d2 = pixel_d2(H + 9 * i, x, y, &u, &v);
+                if (lowpass) {
+                    double mu[2];
+                    projected_centre(T + 9 * i, mu);
+                    const double r2 = lowpass_r2(mu, x, y);
+                    d2 = r2 < d2 ? r2 : d2;
+                }
                 if (!is_candidate(d2, k2[i])) continue;
                 if (m == cap) {
                     cap *= 2;
@@ -605,16 +802,118 @@ int fso_render_pixels(const int32_t* valid, const uint32_t* zkey, const double* 
                 cs[m].zkey = zkey[i];
                 cs[m].idx = (uint32_t)i;
                 cs[m].d2 = d2;
+                cs[m].z = geo ? intersection_depth(T + 9 * i, u, v) : 0.0;
                 ++m;
             }
             qsort(cs, (size_t)m, sizeof(cand_t), cand_cmp);
             int32_t lc;
             nout[j] = blend_pixel(cs, m, k2, opacity, feats, C, &bo, F + j * C, absF + j * C, Tout + j,
-                                  idx + j * kcap, amb + j, nclamp + j, &lc);
+                                  idx + j * kcap, amb + j, nclamp + j, &lc, normals, geo ? geo + j * GEO_LEN : NULL);
         }
         free(cs);
     }
     return status;
+}
+
+/*
+ * Render pixels from sorted tile lists: pixel (px, py) walks the list of its
+ * tile, vals[ranges[2t] .. ranges[2t+1]), t = (py / S) * tiles_x + px / S, in
+ * list order (tile, depth key, index), and blends it as blend_pixel does.
+ * This is the tiled form of Eq. (2): a surfel missing from a tile's list is
+ * never blended there, which is how a tile assignment that misses pixels of a
+ * footprint (the linearised one of Sec. 3.2) changes the image.  With lowpass,
+ * the response is exp(-min(u^2 + v^2, 2 |x - mu|^2) / 2).  pix = NULL renders
+ * every pixel in row-major order; otherwise pix[j] = py * W + px.  geo (NULL
+ * or GEO_LEN doubles per pixel) receives depth and normal outputs, normals
+ * holding 3 doubles per surfel.  Returns -1 if a list names a surfel >= n.
+ */
+int fso_render_lists(const int32_t* valid, const uint32_t* zkey, const double* T, const double* H, const double* k2,
+                     const double* opacity, const double* feats, const double* normals, int64_t n, int C, int W,
+                     int Hh, int S, const uint32_t* vals, const uint32_t* ranges, const int64_t* pix, int64_t npix,
+                     int lowpass, double alpha_min, double alpha_max, double t_stop, int K, int kcap, double* F,
+                     double* absF, double* Tout, int32_t* nout, int32_t* idx, int32_t* amb, int32_t* nclamp,
+                     double* geo)
+{
+    const int tx_n = (W + S - 1) / S;
+    const int64_t m_pix = pix ? npix : (int64_t)W * Hh;
+    blend_opts bo = {alpha_min, alpha_max, t_stop, K, kcap};
+    int status = 0;
+#pragma omp parallel
+    {
+        int64_t cap = 256;
+        cand_t* cs = (cand_t*)malloc(sizeof(cand_t) * cap);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t j = 0; j < m_pix; ++j) {
+            const int64_t p = pix ? pix[j] : j;
+            const int px = (int)(p % W), py = (int)(p / W);
+            const double x = px + 0.5, y = py + 0.5;
+            const int64_t t = (int64_t)(py / S) * tx_n + px / S;
+            const uint32_t e0 = ranges[2 * t], e1 = ranges[2 * t + 1];
+            int64_t m = 0;
+            for (uint32_t e = e0; e < e1; ++e) {
+                const uint32_t i = vals[e];
+                if ((int64_t)i >= n || !valid[i]) {
+#pragma omp atomic write
+                    status = -1;
+                    continue;
+                }
+                double u, v;
+                double d2 = pixel_d2(H + 9 * (int64_t)i, x, y, &u, &v);
+                if (lowpass) {
+                    double mu[2];
+                    projected_centre(T + 9 * (int64_t)i, mu);
+                    const double r2 = lowpass_r2(mu, x, y);
+                    d2 = r2 < d2 ? r2 : d2;
+                }
+                if (m == cap) {
+                    cap *= 2;
+                    cs = (cand_t*)realloc(cs, sizeof(cand_t) * cap);
+                }
+                cs[m].zkey = zkey[i];
+                cs[m].idx = i;
+                cs[m].d2 = d2;
+                cs[m].z = geo ? intersection_depth(T + 9 * (int64_t)i, u, v) : 0.0;
+                ++m;
+            }
+            int32_t lc;
+            nout[j] = blend_pixel(cs, m, k2, opacity, feats, C, &bo, F + j * C, absF + j * C, Tout + j,
+                                  idx + j * kcap, amb + j, nclamp + j, &lc, normals, geo ? geo + j * GEO_LEN : NULL);
+        }
+        free(cs);
+    }
+    return status;
+}
+
+/*
+ * Surfel normals (Sec. 3.1: n = t_u x t_v, the cross product of the tangent
+ * vectors), rotated into camera space (n_c = R n, scaled to unit length: the
+ * camera rotation arrives in float32 and is orthonormal only to ~1e-7) and
+ * flipped where needed so that they face the camera (n_c . p_c <= 0).  Zero
+ * for a zero quaternion or non-finite input.  out: 3 doubles per surfel.
+ */
+int fso_normals(const double* means, const double* quats, int64_t n, const double* cam, double* out)
+{
+    const double* R = cam + CR;
+    for (int64_t i = 0; i < n; ++i) {
+        const double* q = quats + 4 * i;
+        const double* p = means + 3 * i;
+        double* o = out + 3 * i;
+        o[0] = o[1] = o[2] = 0.0;
+        if (!all_finite(q, 4) || !all_finite(p, 3)) continue;
+        const double qq = ((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3];
+        if (!(qq > 0.0)) continue;
+        double tu[3], tv[3], nw[3], nc[3], pc[3];
+        tangent_frame(q, 2.0 / qq, tu, tv);
+        cross3(tu, tv, nw);
+        for (int r = 0; r < 3; ++r) {
+            nc[r] = (R[3 * r] * nw[0] + R[3 * r + 1] * nw[1]) + R[3 * r + 2] * nw[2];
+            pc[r] = ((R[3 * r] * p[0] + R[3 * r + 1] * p[1]) + R[3 * r + 2] * p[2]) + cam[CT + r];
+        }
+        const double len = sqrt(dot3(nc, nc));
+        const double sgn = dot3(nc, pc) > 0.0 ? -1.0 : 1.0;
+        for (int r = 0; r < 3; ++r) o[r] = sgn * nc[r] / len;
+    }
+    return 0;
 }
 
 /*
@@ -676,6 +975,7 @@ int fso_render_image(const int32_t* valid, const uint32_t* zkey, const double* H
                     cs[slot].zkey = zkey[i];
                     cs[slot].idx = (uint32_t)i;
                     cs[slot].d2 = d2;
+                    cs[slot].z = 0.0;
                 }
             }
     }
@@ -686,7 +986,7 @@ int fso_render_image(const int32_t* valid, const uint32_t* zkey, const double* H
         qsort(cs + start[p], (size_t)m, sizeof(cand_t), cand_cmp);
         int32_t lc;
         nout[p] = blend_pixel(cs + start[p], m, k2, opacity, feats, C, &bo, F + p * C, absF + p * C, Tout + p,
-                              idx + p * kcap, amb + p, nclamp + p, &lc);
+                              idx + p * kcap, amb + p, nclamp + p, &lc, NULL, NULL);
     }
     free(start);
     free(cs);
