@@ -88,14 +88,21 @@ typedef struct fs_camera {
     int64_t pixel_offset;   /* first packed pixel of this view (fs_layout_views) */
 } fs_camera;
 
-enum { FS_TILES_PRECISE = 0, FS_TILES_BBOX = 1 };
+enum { FS_TILES_PRECISE = 0, FS_TILES_BBOX = 1, FS_TILES_LINEARISED = 2 };
 enum { FS_FEAT_F32 = 0, FS_FEAT_BF16 = 1 };
 
 typedef struct fs_opts {
     int32_t tile;        /* binning tile side in pixels: 8, 16 or 32 */
     int32_t topk;        /* 0: full blend (Eq. 2); K in [1, 64]: Top-K hard selection (Sec. 3.4) */
     int32_t tile_mode;   /* FS_TILES_PRECISE: exact footprint tiles (SnugBox + AccuTile);
-                            FS_TILES_BBOX: every tile of the ellipse's circumscribed square */
+                            FS_TILES_BBOX: every tile of the ellipse's circumscribed square;
+                            FS_TILES_LINEARISED: the paper-literal assignment of Sec. 3.2 --
+                            tiles holding a pixel centre inside the ellipse of the linearised
+                            projected covariance Sigma' = J J^T, J the Jacobian of the
+                            perspective map at the tangent origin.  Pixels of the exact
+                            footprint outside those tiles are not blended (the renderers
+                            still test the exact footprint), so images can differ from
+                            PRECISE; the other two modes give identical images */
     int32_t feat_dtype;  /* FS_FEAT_F32 or FS_FEAT_BF16 storage of feats (math is float32) */
     float alpha_min;     /* a surfel contributes to a pixel iff o f(u) >= alpha_min (1/255) */
     float alpha_max;     /* alpha = min(alpha_max, o f(u)) (0.99) */
@@ -116,6 +123,12 @@ typedef struct fs_opts {
                             blended front to back with those weights; T_final is the
                             walk's.  FS_TOPK_WEIGHT needs FS_SCHED_SPLIT and topk <= 16
                             (else FS_ERR_UNSUPPORTED) and has no backward. */
+    int32_t lowpass;     /* 1: the screen-space low-pass filter of 2D Gaussian splatting
+                            (not in the paper): the response is exp(-d2 / 2) with
+                            d2 = min(u^2 + v^2, 2 |x - mu|^2), mu the projected centre, so
+                            a surfel also covers the pixel centres within sqrt(k^2 / 2)
+                            px of mu (tiles included).  No backward (FS_ERR_UNSUPPORTED).
+                            0: the pure ray-splat response */
 } fs_opts;
 
 enum { FS_SCHED_GRID = 0, FS_SCHED_PERSISTENT = 1, FS_SCHED_SPLIT = 2 };
@@ -235,7 +248,7 @@ fs_status fs_sort(uint64_t* keys, uint32_t* vals, int64_t pair_capacity, const i
 
 /*
  * fs_render_forward (Sec. 3.1 Eq. 2; Sec. 3.4).  Per pixel, walks its tile's
- * sorted list front to back:
+ * sorted list (keys and vals from fs_sort) front to back:
  *   (u, v) = ray-splat intersection; alpha = min(alpha_max, o exp(-(u^2+v^2)/2));
  *   skip if alpha < alpha_min; stop before a surfel with T (1 - alpha) < t_stop;
  *   w = alpha T; F += w c; T *= 1 - alpha; with topk = K > 0 stop after the
@@ -249,15 +262,28 @@ fs_status fs_sort(uint64_t* keys, uint32_t* vals, int64_t pair_capacity, const i
  *              blended surfel, -1 if none (needed by fs_render_backward)
  *   out_idx    optional out, total_pixels x topk int32 record indices of the
  *              blended surfels front to back, -1 padded (topk > 0 only)
+ *   out_depth  optional out, total_pixels float32: sum of w z over the
+ *              blended surfels, z the camera depth of the ray-splat
+ *              intersection point (divide by 1 - T for the mean depth);
+ *              needs keys (the depth of the centre is read from the key's
+ *              low 32 bits)
+ *   out_normal optional out, total_pixels x 3 float32: sum of w n, n the
+ *              surfel's camera-space unit normal t_u x t_v (Sec. 3.1) turned
+ *              to face the camera
+ *              Depth and normal follow the same blend (and Top-K selection)
+ *              as the features; FS_ERR_UNSUPPORTED with FS_TOPK_WEIGHT.
  *   counters   optional in/out, 4 uint64 added to: [0] list entries walked
  *              (over all 8x8 or 16x16 render blocks), [1] feature rows the
  *              blocks need (one per block and entry blended by any of its
  *              pixels), [2] blended (pixel, surfel) pairs, [3] blocks run
+ *   keys       the sorted keys of fs_sort, read only for out_depth (else NULL)
  */
-fs_status fs_render_forward(const void* records, const uint32_t* vals, const uint32_t* tile_ranges, const void* feats,
-                            int32_t C, int64_t n, const fs_camera* cams_dev, int32_t num_views, int64_t total_tiles,
-                            const fs_opts* opts, float* out_feat, float* out_T, int32_t* out_n, int32_t* out_last,
-                            int32_t* out_idx, uint64_t* counters, void* workspace, hipStream_t stream);
+fs_status fs_render_forward(const void* records, const uint64_t* keys, const uint32_t* vals,
+                            const uint32_t* tile_ranges, const void* feats, int32_t C, int64_t n,
+                            const fs_camera* cams_dev, int32_t num_views, int64_t total_tiles, const fs_opts* opts,
+                            float* out_feat, float* out_T, int32_t* out_n, int32_t* out_last, int32_t* out_idx,
+                            float* out_depth, float* out_normal, uint64_t* counters, void* workspace,
+                            hipStream_t stream);
 
 /*
  * fs_render_labels (Sec. 3.3, Sec. 3.5: segmentation masks come from
@@ -318,7 +344,9 @@ fs_status fs_instance_labels(const float* ins_feats, int32_t dim, const float* m
  * gradient.  grad_records is caller scratch of num_views * n *
  * FS_GRAD_RECORD_FLOATS floats (zeroed by this call).  Gradients are summed
  * with float atomics, so their last bits depend on scheduling.  C <= 128
- * (FS_ERR_UNSUPPORTED above).  The forward outputs out_T / out_last must come
+ * (FS_ERR_UNSUPPORTED above, and for the low-pass option).  Only the feature
+ * image is differentiated (depth and normal outputs carry no gradient).  Any
+ * tile mode works: the backward walks the same lists.  The forward outputs out_T / out_last must come
  * from fs_render_forward on the same records, vals and tile_ranges.  With
  * topk > 0 the selection is recomputed exactly as the forward made it (the
  * transmittance chain in the forward's double-precision order), in

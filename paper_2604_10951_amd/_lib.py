@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libfastsegsim.so")
 
 FS_OK, FS_ERR_ARG, FS_ERR_CAPACITY, FS_ERR_HIP, FS_ERR_UNSUPPORTED, FS_ERR_SCRATCH = 0, 1, 2, 3, 4, 5
 FS_NOALLOC_MAX_RECORDS = 4194304
-FS_TILES_PRECISE, FS_TILES_BBOX = 0, 1
+FS_TILES_PRECISE, FS_TILES_BBOX, FS_TILES_LINEARISED = 0, 1, 2
 FS_FEAT_F32, FS_FEAT_BF16 = 0, 1
 FS_SCHED_GRID, FS_SCHED_PERSISTENT, FS_SCHED_SPLIT = 0, 1, 2
 FS_TOPK_FIRST, FS_TOPK_WEIGHT = 0, 1
@@ -34,11 +34,11 @@ class FsOpts(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("topk", ctypes.c_int32), ("tile_mode", ctypes.c_int32),
                 ("feat_dtype", ctypes.c_int32), ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
                 ("t_stop", ctypes.c_float), ("batch", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("topk_mode", ctypes.c_int32)]
+                ("topk_mode", ctypes.c_int32), ("lowpass", ctypes.c_int32)]
 
 
 assert ctypes.sizeof(FsCamera) == 88
-assert ctypes.sizeof(FsOpts) == 40
+assert ctypes.sizeof(FsOpts) == 44
 
 
 class FastSegSimError(RuntimeError):
@@ -66,7 +66,8 @@ SIGNATURES = {
     "fs_bin_noalloc": ([P, P, P, P, I64, P, I32, ctypes.POINTER(FsOpts), P, P, P, P, I64, P, ctypes.POINTER(I64), P],
                        I32),
     "fs_sort": ([P, P, I64, P, I64, I64, P, P, P], I32),
-    "fs_render_forward": ([P, P, P, P, I32, I64, P, I32, I64, ctypes.POINTER(FsOpts), P, P, P, P, P, P, P, P], I32),
+    "fs_render_forward": ([P, P, P, P, P, I32, I64, P, I32, I64, ctypes.POINTER(FsOpts), P, P, P, P, P, P, P, P, P,
+                           P], I32),
     "fs_render_labels": ([P, P, P, P, I32, I64, P, I32, I64, ctypes.POINTER(FsOpts), P, P, P, P, P, P, P], I32),
     "fs_instance_labels": ([P, I32, P, I64, P, P, P, I32, P, P], I32),
     "fs_render_backward": ([P, P, P, P, P, P, P, P, I32, I64, P, I32, I64, ctypes.POINTER(FsOpts), P, P, P, P, P, P,
@@ -104,8 +105,10 @@ def check(status: int, what: str) -> None:
 
 def make_opts(tile: int = 16, topk: int = 0, tile_mode: int = FS_TILES_PRECISE, feat_dtype: int = FS_FEAT_F32,
               alpha_min: float = 1.0 / 255.0, alpha_max: float = 0.99, t_stop: float = 1e-4,
-              batch: int = 0, schedule: int = FS_SCHED_GRID, topk_mode: int = FS_TOPK_FIRST) -> FsOpts:
-    return FsOpts(tile, topk, tile_mode, feat_dtype, alpha_min, alpha_max, t_stop, batch, schedule, topk_mode)
+              batch: int = 0, schedule: int = FS_SCHED_GRID, topk_mode: int = FS_TOPK_FIRST,
+              lowpass: int = 0) -> FsOpts:
+    return FsOpts(tile, topk, tile_mode, feat_dtype, alpha_min, alpha_max, t_stop, batch, schedule, topk_mode,
+                  lowpass)
 
 
 def make_cameras(cams, tile: int):

@@ -20,7 +20,9 @@ bool valid_opts(const fs_opts* o) {
     if (!o) return false;
     if (o->tile != 8 && o->tile != 16 && o->tile != 32) return false;
     if (o->topk < 0 || o->topk > 64) return false;
-    if (o->tile_mode != FS_TILES_PRECISE && o->tile_mode != FS_TILES_BBOX) return false;
+    if (o->tile_mode != FS_TILES_PRECISE && o->tile_mode != FS_TILES_BBOX && o->tile_mode != FS_TILES_LINEARISED)
+        return false;
+    if (o->lowpass != 0 && o->lowpass != 1) return false;
     if (o->feat_dtype != FS_FEAT_F32 && o->feat_dtype != FS_FEAT_BF16) return false;
     if (!(o->alpha_min > 0.f) || !(o->alpha_max <= 1.f) || !(o->alpha_min < o->alpha_max)) return false;
     if (!(o->t_stop >= 0.f) || !(o->t_stop < 1.f)) return false;
@@ -216,14 +218,19 @@ fs_status fs_sort(uint64_t* keys, uint32_t* vals, int64_t pair_capacity, const i
         fs_launch_sort(keys, vals, pair_capacity, num_pairs_dev, num_pairs_hint, total_tiles, tile_ranges, ws, stream));
 }
 
-fs_status fs_render_forward(const void* records, const uint32_t* vals, const uint32_t* tile_ranges, const void* feats,
-                            int32_t C, int64_t n, const fs_camera* cams_dev, int32_t num_views, int64_t total_tiles,
-                            const fs_opts* opts, float* out_feat, float* out_T, int32_t* out_n, int32_t* out_last,
-                            int32_t* out_idx, uint64_t* counters, void* workspace, hipStream_t stream) {
+fs_status fs_render_forward(const void* records, const uint64_t* keys, const uint32_t* vals,
+                            const uint32_t* tile_ranges, const void* feats, int32_t C, int64_t n,
+                            const fs_camera* cams_dev, int32_t num_views, int64_t total_tiles, const fs_opts* opts,
+                            float* out_feat, float* out_T, int32_t* out_n, int32_t* out_last, int32_t* out_idx,
+                            float* out_depth, float* out_normal, uint64_t* counters, void* workspace,
+                            hipStream_t stream) {
     if (!valid_opts(opts) || C < 1 || n < 1 || num_views < 1 || total_tiles < 1 || !cams_dev) return FS_ERR_ARG;
     if (!records || !tile_ranges || !feats || !out_feat || !out_T || !out_n) return FS_ERR_ARG;
     if (out_idx && opts->topk < 1) return FS_ERR_ARG;
+    if (out_depth && !keys) return FS_ERR_ARG;
     if (C > 1024 || unsupported_opts(opts)) return FS_ERR_UNSUPPORTED;
+    const bool ext = opts->lowpass != 0 || out_depth || out_normal;
+    if (ext && opts->topk_mode == FS_TOPK_WEIGHT) return FS_ERR_UNSUPPORTED;
     FsWorkspace ws;
     memset(&ws, 0, sizeof(ws));
     if (opts->schedule != FS_SCHED_GRID) {
@@ -231,13 +238,13 @@ fs_status fs_render_forward(const void* records, const uint32_t* vals, const uin
         if (!fs_workspace_layout(workspace, 0, 1, total_tiles, 0, opts, &ws, nullptr)) return FS_ERR_ARG;
     }
     if (opts->schedule == FS_SCHED_SPLIT)
-        return hip_status(fs_launch_render_topk_split(static_cast<const FsRecord*>(records), vals, tile_ranges, feats,
-                                                      C, n, cams_dev, num_views, total_tiles, *opts, out_feat,
-                                                      nullptr, nullptr, out_T, out_n, out_last, out_idx, counters, ws,
-                                                      stream));
-    return hip_status(fs_launch_render_forward(static_cast<const FsRecord*>(records), vals, tile_ranges, feats, C, n,
-                                               cams_dev, num_views, total_tiles, *opts, out_feat, out_T, out_n,
-                                               out_last, out_idx, counters, ws, stream));
+        return hip_status(fs_launch_render_topk_split(static_cast<const FsRecord*>(records), keys, vals, tile_ranges,
+                                                      feats, C, n, cams_dev, num_views, total_tiles, *opts, out_feat,
+                                                      nullptr, nullptr, out_T, out_n, out_last, out_idx, out_depth,
+                                                      out_normal, counters, ws, stream));
+    return hip_status(fs_launch_render_forward(static_cast<const FsRecord*>(records), keys, vals, tile_ranges, feats,
+                                               C, n, cams_dev, num_views, total_tiles, *opts, out_feat, out_T, out_n,
+                                               out_last, out_idx, out_depth, out_normal, counters, ws, stream));
 }
 
 fs_status fs_render_labels(const void* records, const uint32_t* vals, const uint32_t* tile_ranges, const void* feats,
@@ -247,12 +254,14 @@ fs_status fs_render_labels(const void* records, const uint32_t* vals, const uint
     if (!valid_opts(opts) || C < 1 || n < 1 || num_views < 1 || total_tiles < 1 || !cams_dev) return FS_ERR_ARG;
     if (!records || !tile_ranges || !feats || !out_label || !out_T || !out_n || !workspace) return FS_ERR_ARG;
     if (C > 1024 || unsupported_opts(opts) || opts->schedule != FS_SCHED_SPLIT) return FS_ERR_UNSUPPORTED;
+    if (opts->lowpass != 0 && opts->topk_mode == FS_TOPK_WEIGHT) return FS_ERR_UNSUPPORTED;
     FsWorkspace ws;
     memset(&ws, 0, sizeof(ws));
     if (!fs_workspace_layout(workspace, 0, 1, total_tiles, 0, opts, &ws, nullptr)) return FS_ERR_ARG;
-    return hip_status(fs_launch_render_topk_split(static_cast<const FsRecord*>(records), vals, tile_ranges, feats, C,
-                                                  n, cams_dev, num_views, total_tiles, *opts, nullptr, out_label,
-                                                  out_score, out_T, out_n, nullptr, nullptr, counters, ws, stream));
+    return hip_status(fs_launch_render_topk_split(static_cast<const FsRecord*>(records), nullptr, vals, tile_ranges,
+                                                  feats, C, n, cams_dev, num_views, total_tiles, *opts, nullptr,
+                                                  out_label, out_score, out_T, out_n, nullptr, nullptr, nullptr,
+                                                  nullptr, counters, ws, stream));
 }
 
 fs_status fs_instance_labels(const float* ins_feats, int32_t dim, const float* means, int64_t n,
@@ -283,6 +292,7 @@ fs_status fs_render_backward(const float* means, const float* scales, const floa
         return FS_ERR_ARG;
     if (C > 128) return FS_ERR_UNSUPPORTED;   // one channel chunk per block in the backward
     if (opts->topk_mode == FS_TOPK_WEIGHT) return FS_ERR_UNSUPPORTED;   // no backward of the by-weight selection
+    if (opts->lowpass != 0) return FS_ERR_UNSUPPORTED;                 // no backward of the low-pass response
     FsWorkspace ws;
     memset(&ws, 0, sizeof(ws));
     if (opts->topk > 0) {

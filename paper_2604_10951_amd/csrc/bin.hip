@@ -230,7 +230,9 @@ bin_kernel(const float* __restrict__ means, const float* __restrict__ scales, co
 }
 
 // Footprints whose tiles the cache does not hold: one lane per record,
-// re-derived from the parameters with the code fs_preprocess counted them with.
+// re-derived from the parameters with the code fs_preprocess counted them with
+// (EXT: the linearised tile mode or the low-pass option).
+template <bool EXT>
 __global__ void __launch_bounds__(kThreads)
 bin_overflow_kernel(const float* __restrict__ means, const float* __restrict__ scales,
                     const float* __restrict__ quats, const float* __restrict__ opacity, int64_t n,
@@ -250,7 +252,8 @@ bin_overflow_kernel(const float* __restrict__ means, const float* __restrict__ s
         FsFootprint fp;
         if (!fs_project(means + 3 * i, scales + 2 * i, quats + 4 * i, opacity[i], cam, (double)o.alpha_min, g))
             continue;
-        if (!fs_footprint(g, cam.width, cam.height, fp)) continue;
+        const bool exact_ok = fs_footprint(g, cam.width, cam.height, fp);
+        if (!EXT && !exact_ok) continue;
         const uint64_t zk = g.zkey;
         const int64_t toff = cam.tile_offset;
         uint64_t o0 = e.y;
@@ -262,7 +265,19 @@ bin_overflow_kernel(const float* __restrict__ means, const float* __restrict__ s
             }
             ++o0;
         };
-        if (o.tile_mode == FS_TILES_BBOX) {
+        if constexpr (EXT) {
+            FsAssign a;
+            fs_assign_setup(g, fp, exact_ok, cam.width, cam.height, o.tile_mode == FS_TILES_LINEARISED,
+                            o.lowpass != 0, a);
+            if (o.tile_mode == FS_TILES_BBOX) {
+                int tx0, tx1, ty0, ty1;
+                if (fs_bbox_tiles_ext(fp, exact_ok, a, cam.width, cam.height, S, tx0, tx1, ty0, ty1))
+                    for (int ty = ty0; ty <= ty1; ++ty)
+                        for (int tx = tx0; tx <= tx1; ++tx) emit(tx, ty);
+            } else {
+                fs_sweep_tiles_ext(fp, a, S, emit);
+            }
+        } else if (o.tile_mode == FS_TILES_BBOX) {
             int tx0, tx1, ty0, ty1;
             if (fs_bbox_tiles(fp, cam.width, cam.height, S, tx0, tx1, ty0, ty1))
                 for (int ty = ty0; ty <= ty1; ++ty)
@@ -293,7 +308,9 @@ hipError_t fs_launch_bin(const float* means, const float* scales, const float* q
     // overflow records: a grid of about one lane per 16 records, each lane striding
     const int64_t ob = (items / 16 + kThreads - 1) / kThreads;
     const unsigned oblocks = (unsigned)(ob < 1 ? 1 : (ob > 4096 ? 4096 : ob));
-    hipLaunchKernelGGL(bin_overflow_kernel, dim3(oblocks), dim3(kThreads), 0, s, means, scales, quats, opacity, n, cams,
-                       o, tiles_touched, ws.bin_overflow, ws.scan_ticket, keys, vals, capacity);
+    const bool ext = o.tile_mode == FS_TILES_LINEARISED || o.lowpass != 0;
+    hipLaunchKernelGGL(ext ? bin_overflow_kernel<true> : bin_overflow_kernel<false>, dim3(oblocks), dim3(kThreads), 0,
+                       s, means, scales, quats, opacity, n, cams, o, tiles_touched, ws.bin_overflow, ws.scan_ticket,
+                       keys, vals, capacity);
     return hipGetLastError();
 }

@@ -275,14 +275,15 @@ FS_DEV bool fs_footprint(const FsGeo& g, int W, int Hh, FsFootprint& fp) {
     return fp.px0 <= fp.px1 && fp.py0 <= fp.py1;
 }
 
-// Pixels of one line inside the footprint.  Row mode (rows = true): line is
+// Pixels of one line inside a conic shape.  Row mode (rows = true): line is
 // pixel row `l`, the result [lo, hi] are pixel columns.  Column mode: line is
 // pixel column `l`, result are pixel rows.  The quadratic (the AccuTile
 // equation of Sec. 3.2) gives the interval; endpoint pixels whose centres lie
-// within 1e-4 px of the conic are re-decided with the exact predicate, so the
-// result equals the per-pixel definition.  Returns false if the line is empty.
-FS_DEV bool fs_line_interval(const FsFootprint& fp, bool rows, int l, int lo_lim, int hi_lim, int& lo, int& hi) {
-    const FsConic& q = fp.q;
+// within 1e-4 px of the conic are re-decided with the shape's exact
+// predicate pin(s), so the result equals the per-pixel definition.  Returns
+// false if the line is empty.
+template <class Pin>
+FS_DEV bool fs_conic_line(const FsConic& q, Pin&& pin, bool rows, int l, int lo_lim, int hi_lim, int& lo, int& hi) {
     // along-line coordinate s, across-line offset d (both anchor-relative)
     double a, b, c, d;
     int anchor_s;
@@ -304,8 +305,7 @@ FS_DEV bool fs_line_interval(const FsFootprint& fp, bool rows, int l, int lo_lim
         lo = hi_lim + 1;
         hi = lo_lim - 1;
         for (int s = lo_lim; s <= hi_lim; ++s) {
-            const bool in = rows ? fs_pixel_in(fp.H, fp.k2, s, l) : fs_pixel_in(fp.H, fp.k2, l, s);
-            if (in) {
+            if (pin(s)) {
                 lo = lo < s ? lo : s;
                 hi = s;
             }
@@ -314,7 +314,6 @@ FS_DEV bool fs_line_interval(const FsFootprint& fp, bool rows, int l, int lo_lim
     }
     const double eps = 1e-4;
     const double disc = b * b - a * c;
-    auto pin = [&](int s) -> bool { return rows ? fs_pixel_in(fp.H, fp.k2, s, l) : fs_pixel_in(fp.H, fp.k2, l, s); };
     if (disc < 0.0) {
         // empty unless the line is tangent within rounding: test the pixel
         // nearest the vertex and grow from it
@@ -371,6 +370,13 @@ FS_DEV bool fs_line_interval(const FsFootprint& fp, bool rows, int l, int lo_lim
     lo = (int)L;
     hi = (int)Hi;
     return true;
+}
+
+// Pixels of one line inside the exact footprint (fs_conic_line with the
+// footprint predicate u^2 + v^2 <= k^2).
+FS_DEV bool fs_line_interval(const FsFootprint& fp, bool rows, int l, int lo_lim, int hi_lim, int& lo, int& hi) {
+    auto pin = [&](int s) -> bool { return rows ? fs_pixel_in(fp.H, fp.k2, s, l) : fs_pixel_in(fp.H, fp.k2, l, s); };
+    return fs_conic_line(fp.q, pin, rows, l, lo_lim, hi_lim, lo, hi);
 }
 
 // Enumerate the tiles of the footprint (SnugBox traversal: lines run along the
@@ -443,6 +449,237 @@ FS_DEV bool fs_bbox_tiles(const FsFootprint& fp, int W, int Hh, int S, int& tx0,
 }
 
 // ---------------------------------------------------------------------------
+// Extended tile assignment: the paper-literal linearised ellipse (Sec. 3.2)
+// in place of the exact footprint, and the low-pass disc (2D Gaussian
+// splatting's screen-space filter) added to either.  Every predicate is
+// evaluated in double precision with a fixed operation order, so the tile
+// sets are a pure function of the inputs.
+// ---------------------------------------------------------------------------
+// The linearised projected covariance, read as J J^T with J the Jacobian of
+// the perspective map (T1 . u, T2 . u) / (Tw . u) at the tangent origin:
+// J_rc = (T_rc - mu_r T_wc) / T_w3, mu = (T_13, T_23) / T_w3.  P receives the
+// inverse of Sigma' = J J^T as (P00, P01, P11); false if Sigma' is singular.
+FS_DEV bool fs_linearised_ellipse(const double T[9], double mu[2], double P[3]) {
+    mu[0] = T[2] / T[8];
+    mu[1] = T[5] / T[8];
+    const double J00 = (T[0] - mu[0] * T[6]) / T[8];
+    const double J01 = (T[1] - mu[0] * T[7]) / T[8];
+    const double J10 = (T[3] - mu[1] * T[6]) / T[8];
+    const double J11 = (T[4] - mu[1] * T[7]) / T[8];
+    const double S00 = J00 * J00 + J01 * J01;
+    const double S01 = J00 * J10 + J01 * J11;
+    const double S11 = J10 * J10 + J11 * J11;
+    const double det = S00 * S11 - S01 * S01;
+    if (!(det > 0.0) || !fs_finite(det)) return false;
+    P[0] = S11 / det;
+    P[1] = -S01 / det;
+    P[2] = S00 / det;
+    return true;
+}
+
+// (x - mu)^T Sigma'^-1 (x - mu) <= k^2 at the centre of pixel (px, py).
+FS_DEV bool fs_lin_in(const double mu[2], const double P[3], double k2, int px, int py) {
+    const double dx = ((double)px + 0.5) - mu[0], dy = ((double)py + 0.5) - mu[1];
+    return (P[0] * dx * dx + 2.0 * P[1] * dx * dy) + P[2] * dy * dy <= k2;
+}
+
+// Low-pass disc: 2 |x - mu|^2 <= k^2 at the centre of pixel (px, py).
+FS_DEV bool fs_disc_in(const double mu[2], double k2, int px, int py) {
+    const double dx = ((double)px + 0.5) - mu[0], dy = ((double)py + 0.5) - mu[1];
+    return 2.0 * (dx * dx + dy * dy) <= k2;
+}
+
+// Conic of (x - c)^T P (x - c) <= k2 (P = (P00, P01, P11)) relative to the
+// anchor pixel centre of `like`: only locates line intervals, whose ends the
+// shape's predicate re-decides.
+FS_DEV void fs_centred_conic(const double c[2], const double P[3], double k2, const FsConic& like, FsConic& q) {
+    const double ex = c[0] - ((double)like.ax + 0.5), ey = c[1] - ((double)like.ay + 0.5);
+    q.A = P[0];
+    q.B = P[1];
+    q.C = P[2];
+    q.D = -(P[0] * ex + P[1] * ey);
+    q.E = -(P[1] * ex + P[2] * ey);
+    q.F = (P[0] * ex * ex + 2.0 * P[1] * ex * ey + P[2] * ey * ey) - k2;
+    q.ax = like.ax;
+    q.ay = like.ay;
+}
+
+// Candidate pixel range of a conic (extent widened by one pixel, clamped to
+// the image; the whole image if the extent is not finite).  False if it lies
+// outside the image.
+FS_DEV bool fs_conic_range(const FsConic& q, int W, int Hh, int r[4]) {
+    double e[4];
+    if (!fs_conic_extent(q, e)) {
+        r[0] = 0;
+        r[1] = W - 1;
+        r[2] = 0;
+        r[3] = Hh - 1;
+        return true;
+    }
+    const double big = 4.0e6;
+    for (int j = 0; j < 4; ++j) e[j] = e[j] < -big ? -big : (e[j] > big ? big : e[j]);
+    const long long x0 = (long long)ceil(e[0]) + q.ax - 1, x1 = (long long)floor(e[1]) + q.ax + 1;
+    const long long y0 = (long long)ceil(e[2]) + q.ay - 1, y1 = (long long)floor(e[3]) + q.ay + 1;
+    if (x1 < 0 || x0 > W - 1 || y1 < 0 || y0 > Hh - 1) return false;
+    r[0] = fs_clampi(x0, 0, W - 1);
+    r[1] = fs_clampi(x1, 0, W - 1);
+    r[2] = fs_clampi(y0, 0, Hh - 1);
+    r[3] = fs_clampi(y1, 0, Hh - 1);
+    return r[0] <= r[1] && r[2] <= r[3];
+}
+
+FS_DEV void fs_range_union(int r[4], const int a[4], bool& have) {
+    if (!have) {
+        for (int j = 0; j < 4; ++j) r[j] = a[j];
+        have = true;
+        return;
+    }
+    r[0] = a[0] < r[0] ? a[0] : r[0];
+    r[1] = a[1] > r[1] ? a[1] : r[1];
+    r[2] = a[2] < r[2] ? a[2] : r[2];
+    r[3] = a[3] > r[3] ? a[3] : r[3];
+}
+
+// The shapes a surfel's tiles come from when the tile mode is LINEARISED or
+// the low-pass option is on, and the pixel box the renderers accept it in.
+struct FsAssign {
+    bool lin;          // the linearised ellipse replaces the exact footprint
+    bool lin_ok;       // Sigma' is positive definite
+    bool exact_ok;     // the exact footprint's range meets the image
+    bool disc;         // the low-pass disc is added
+    double mu[2];      // projected centre
+    double P[3];       // Sigma'^-1
+    FsConic ql, qd;    // linearised and disc conics (anchored like the footprint)
+    int ar[4];         // candidate pixel range of the assignment (x0, x1, y0, y1)
+    bool have_ar;
+    int box[4];        // acceptance box of the record: exact range, plus the disc's
+    bool have_box;
+};
+
+// Set up the extended assignment of a projected surfel whose exact
+// footprint fp was built by fs_footprint (exact_ok = its result).
+FS_DEV void fs_assign_setup(const FsGeo& g, const FsFootprint& fp, bool exact_ok, int W, int Hh, bool lin,
+                            bool lowpass, FsAssign& a) {
+    a.lin = lin;
+    a.disc = lowpass;
+    a.exact_ok = exact_ok;
+    a.lin_ok = false;
+    a.have_ar = a.have_box = false;
+    a.mu[0] = g.T[2] / g.T[8];
+    a.mu[1] = g.T[5] / g.T[8];
+    int r[4];
+    if (exact_ok) {
+        r[0] = fp.px0;
+        r[1] = fp.px1;
+        r[2] = fp.py0;
+        r[3] = fp.py1;
+        fs_range_union(a.box, r, a.have_box);
+        if (!lin) fs_range_union(a.ar, r, a.have_ar);
+    }
+    if (lin) {
+        a.lin_ok = fs_linearised_ellipse(g.T, a.mu, a.P);
+        if (a.lin_ok) {
+            fs_centred_conic(a.mu, a.P, g.k2, fp.q, a.ql);
+            if (fs_conic_range(a.ql, W, Hh, r)) fs_range_union(a.ar, r, a.have_ar);
+        }
+    }
+    if (lowpass) {
+        const double Pd[3] = {2.0, 0.0, 2.0};
+        fs_centred_conic(a.mu, Pd, g.k2, fp.q, a.qd);
+        if (fs_conic_range(a.qd, W, Hh, r)) {
+            fs_range_union(a.ar, r, a.have_ar);
+            fs_range_union(a.box, r, a.have_box);
+        }
+    }
+}
+
+// Tiles of the extended assignment, as fs_sweep_tiles: per tile line the
+// tile spans of every shape's pixel lines are OR-ed into a 64-bit mask.
+template <class Visit>
+FS_DEV void fs_sweep_tiles_ext(const FsFootprint& fp, const FsAssign& a, int S, Visit&& visit) {
+    if (!a.have_ar) return;
+    const int* ar = a.ar;
+    const bool rows = (ar[3] - ar[2]) <= (ar[1] - ar[0]);
+    const int l0 = rows ? ar[2] : ar[0], l1 = rows ? ar[3] : ar[1];
+    const int s0 = rows ? ar[0] : ar[2], s1 = rows ? ar[1] : ar[3];
+    const int ts0 = s0 / S, ts1 = s1 / S;
+    const bool use_exact = !a.lin && a.exact_ok, use_lin = a.lin && a.lin_ok, use_disc = a.disc;
+    for (int wbase = ts0; wbase <= ts1; wbase += 64) {
+        for (int tl = l0 / S; tl <= l1 / S; ++tl) {
+            uint64_t mask = 0;
+            const int la = tl * S > l0 ? tl * S : l0;
+            const int lb = tl * S + S - 1 < l1 ? tl * S + S - 1 : l1;
+            auto add = [&](int lo, int hi) {
+                int t1 = lo / S - wbase, t2 = hi / S - wbase;
+                if (t2 < 0 || t1 > 63) return;
+                t1 = t1 < 0 ? 0 : t1;
+                t2 = t2 > 63 ? 63 : t2;
+                const uint64_t hiBits = (t2 == 63) ? ~0ull : ((1ull << (t2 + 1)) - 1ull);
+                mask |= hiBits & ~((1ull << t1) - 1ull);
+            };
+            for (int l = la; l <= lb; ++l) {
+                int lo, hi;
+                if (use_exact && fs_line_interval(fp, rows, l, s0, s1, lo, hi)) add(lo, hi);
+                if (use_lin) {
+                    auto pin = [&](int t) -> bool {
+                        return rows ? fs_lin_in(a.mu, a.P, fp.k2, t, l) : fs_lin_in(a.mu, a.P, fp.k2, l, t);
+                    };
+                    if (fs_conic_line(a.ql, pin, rows, l, s0, s1, lo, hi)) add(lo, hi);
+                }
+                if (use_disc) {
+                    auto pin = [&](int t) -> bool {
+                        return rows ? fs_disc_in(a.mu, fp.k2, t, l) : fs_disc_in(a.mu, fp.k2, l, t);
+                    };
+                    if (fs_conic_line(a.qd, pin, rows, l, s0, s1, lo, hi)) add(lo, hi);
+                }
+            }
+            while (mask) {
+                const int b = __builtin_ctzll(mask);
+                mask &= mask - 1ull;
+                const int ts = wbase + b;
+                if (rows)
+                    visit(ts, tl);
+                else
+                    visit(tl, ts);
+            }
+        }
+    }
+}
+
+// Bounding-box assignment with the low-pass disc: the tile rectangle
+// covering the exact footprint's circumscribed square and the disc's square.
+FS_DEV bool fs_bbox_tiles_ext(const FsFootprint& fp, bool exact_ok, const FsAssign& a, int W, int Hh, int S,
+                              int& tx0, int& tx1, int& ty0, int& ty1) {
+    bool have = exact_ok && fs_bbox_tiles(fp, W, Hh, S, tx0, tx1, ty0, ty1);
+    if (a.disc) {
+        const double rd = sqrt(0.5 * fp.k2) * (1.0 + 1e-9) + 1e-6;
+        const double lo_x = a.mu[0] - 0.5 - rd, hi_x = a.mu[0] - 0.5 + rd;   // pixel-index units
+        const double lo_y = a.mu[1] - 0.5 - rd, hi_y = a.mu[1] - 0.5 + rd;
+        if (fs_finite(lo_x) && fs_finite(hi_x) && fs_finite(lo_y) && fs_finite(hi_y)) {
+            const long long x0 = (long long)ceil(lo_x), x1 = (long long)floor(hi_x);
+            const long long y0 = (long long)ceil(lo_y), y1 = (long long)floor(hi_y);
+            if (!(x1 < 0 || y1 < 0 || x0 > W - 1 || y0 > Hh - 1 || x0 > x1 || y0 > y1)) {
+                const int dx0 = fs_clampi(x0, 0, W - 1) / S, dx1 = fs_clampi(x1, 0, W - 1) / S;
+                const int dy0 = fs_clampi(y0, 0, Hh - 1) / S, dy1 = fs_clampi(y1, 0, Hh - 1) / S;
+                if (!have) {
+                    tx0 = dx0;
+                    tx1 = dx1;
+                    ty0 = dy0;
+                    ty1 = dy1;
+                    have = true;
+                } else {
+                    tx0 = dx0 < tx0 ? dx0 : tx0;
+                    tx1 = dx1 > tx1 ? dx1 : tx1;
+                    ty0 = dy0 < ty0 ? dy0 : ty0;
+                    ty1 = dy1 > ty1 ? dy1 : ty1;
+                }
+            }
+        }
+    }
+    return have;
+}
+
+// ---------------------------------------------------------------------------
 // Response of a record at pixel offset (dx, dy) from its anchor: (u, v) and
 // d2 = u^2 + v^2 in double precision (fused multiply-adds; 1/h2 from the
 // hardware reciprocal refined by one Newton step).  Shared by the forward and
@@ -464,6 +701,37 @@ FS_DEV FsResp fs_response(const FsRecord& r, double dx, double dy) {
     o.v = h1 * rh;
     o.d2 = fma(o.u, o.u, o.v * o.v);
     return o;
+}
+
+// Projected centre of a record relative to its anchor pixel centre: the
+// point where h0 = h1 = 0 (the tangent origin), solved from the anchored
+// coefficients.  Used by the low-pass response.
+FS_DEV void fs_record_centre(const FsRecord& r, double& mx, double& my) {
+    const double det = r.gx0 * r.gy1 - r.gy0 * r.gx1;
+    mx = (r.h1 * r.gy0 - r.h0 * r.gy1) / det;
+    my = (r.h0 * r.gx1 - r.h1 * r.gx0) / det;
+}
+
+// The low-pass response: d2 = min(u^2 + v^2, 2 |x - mu|^2), the pixel offset
+// (dx, dy) and the centre (mx, my) both relative to the anchor.
+FS_DEV void fs_lowpass_d2(FsResp& rs, double dx, double dy, double mx, double my) {
+    const double ex = dx - mx, ey = dy - my;
+    const double r2 = 2.0 * (ex * ex + ey * ey);
+    rs.d2 = r2 < rs.d2 ? r2 : rs.d2;
+}
+
+// Camera-space normal of a record's plane, facing the camera.  The anchored,
+// normalised h2 equals z_c / depth(x) along the ray of pixel point x, a
+// linear function of x whose gradient, scaled by the focal lengths, and whose
+// value at the principal point form a normal m with m . p_c > 0: the
+// camera-facing unit normal is -m / |m|.  (cx, cy) are in pixel-index units
+// relative to the anchor pixel centre.
+FS_DEV float3 fs_record_normal(const FsRecord& r, const fs_camera& cam) {
+    const double ox = (double)cam.cx - ((double)r.ax + 0.5), oy = (double)cam.cy - ((double)r.ay + 0.5);
+    const double m0 = (double)cam.fx * r.gx2, m1 = (double)cam.fy * r.gy2;
+    const double m2 = r.h2 + ox * r.gx2 + oy * r.gy2;
+    const double inv = -1.0 / sqrt(m0 * m0 + m1 * m1 + m2 * m2);
+    return make_float3((float)(m0 * inv), (float)(m1 * inv), (float)(m2 * inv));
 }
 
 // A pixel is accepted only inside the record's pixel box (it holds every
@@ -649,10 +917,11 @@ hipError_t fs_noalloc_scratch(void** ptr, size_t* bytes);
 hipError_t fs_launch_sort(uint64_t* keys, uint32_t* vals, int64_t capacity, const int64_t* num_pairs, int64_t hint,
                           int64_t total_tiles, uint32_t* ranges, const FsWorkspace& ws, hipStream_t s);
 
-hipError_t fs_launch_render_forward(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges,
-                                    const void* feats, int C, int64_t n, const fs_camera* cams, int num_views,
-                                    int64_t total_tiles, const fs_opts& o, float* out_feat, float* out_T,
-                                    int32_t* out_n, int32_t* out_last, int32_t* out_idx, uint64_t* counters,
+hipError_t fs_launch_render_forward(const FsRecord* records, const uint64_t* keys, const uint32_t* vals,
+                                    const uint32_t* ranges, const void* feats, int C, int64_t n,
+                                    const fs_camera* cams, int num_views, int64_t total_tiles, const fs_opts& o,
+                                    float* out_feat, float* out_T, int32_t* out_n, int32_t* out_last,
+                                    int32_t* out_idx, float* out_depth, float* out_normal, uint64_t* counters,
                                     const FsWorkspace& ws, hipStream_t s);
 
 // Work order of render blocks (tile list length, longest first; ties in any
@@ -663,9 +932,10 @@ hipError_t fs_launch_block_order(const uint32_t* ranges, int sb2, uint32_t nbloc
 // Selection pass of the split Top-K renderer alone: per-pixel (slot, weight)
 // lists, block row lists and counts in the workspace; out_T, out_last,
 // out_idx and counters optional.
-hipError_t fs_launch_topk_select(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges, int64_t n,
-                                 const fs_camera* cams, int num_views, int64_t total_tiles, const fs_opts& o,
-                                 float* out_T, int32_t* out_n, int32_t* out_last, int32_t* out_idx,
+hipError_t fs_launch_topk_select(const FsRecord* records, const uint64_t* keys, const uint32_t* vals,
+                                 const uint32_t* ranges, int64_t n, const fs_camera* cams, int num_views,
+                                 int64_t total_tiles, const fs_opts& o, float* out_T, int32_t* out_n,
+                                 int32_t* out_last, int32_t* out_idx, float* out_depth, float* out_normal,
                                  uint64_t* counters, const FsWorkspace& ws, hipStream_t s);
 
 // Per-Gaussian instance labels (softmax over queries of similarity x
@@ -675,11 +945,13 @@ hipError_t fs_launch_instance_labels(const float* fins, int D, const float* mean
 
 // Both passes of the split Top-K renderer.  Exactly one of out_feat (feature
 // image) and out_label (per-pixel channel argmax, out_score optional) is set.
-hipError_t fs_launch_render_topk_split(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges,
-                                       const void* feats, int C, int64_t n, const fs_camera* cams, int num_views,
-                                       int64_t total_tiles, const fs_opts& o, float* out_feat, int32_t* out_label,
-                                       float* out_score, float* out_T, int32_t* out_n, int32_t* out_last,
-                                       int32_t* out_idx, uint64_t* counters, const FsWorkspace& ws, hipStream_t s);
+hipError_t fs_launch_render_topk_split(const FsRecord* records, const uint64_t* keys, const uint32_t* vals,
+                                       const uint32_t* ranges, const void* feats, int C, int64_t n,
+                                       const fs_camera* cams, int num_views, int64_t total_tiles, const fs_opts& o,
+                                       float* out_feat, int32_t* out_label, float* out_score, float* out_T,
+                                       int32_t* out_n, int32_t* out_last, int32_t* out_idx, float* out_depth,
+                                       float* out_normal, uint64_t* counters, const FsWorkspace& ws,
+                                       hipStream_t s);
 
 hipError_t fs_launch_render_backward(const float* means, const float* scales, const float* quats,
                                      const float* opacity, const FsRecord* records, const uint32_t* vals,

@@ -42,12 +42,38 @@ FS_DEV bool fs_outside_view(const float* pm, const float* ps, float op, const fs
            yt + rho * (fabs(fy) + fabs(cy)) < 0.0 || yb - rho * (fabs(fy) + fabs(cy - H)) > 0.0;
 }
 
+// Render coefficients of a projected surfel, anchored at fp's anchor pixel
+// and normalised (h2 = 1 at the projected centre); the pixel box is left to
+// the caller.
+FS_DEV void fs_fill_record(const FsGeo& g, const FsFootprint& fp, float op, FsRecord& rec) {
+    const double mx = g.T[2] / g.T[8], my = g.T[5] / g.T[8];
+    const double s = (g.H[6] * mx + g.H[7] * my) + g.H[8];
+    const double is = 1.0 / s;
+    const double xa = fp.q.ax + 0.5, ya = fp.q.ay + 0.5;
+    rec.h0 = ((g.H[0] * xa + g.H[1] * ya) + g.H[2]) * is;
+    rec.h1 = ((g.H[3] * xa + g.H[4] * ya) + g.H[5]) * is;
+    rec.h2 = ((g.H[6] * xa + g.H[7] * ya) + g.H[8]) * is;
+    rec.gx0 = g.H[0] * is;
+    rec.gx1 = g.H[3] * is;
+    rec.gx2 = g.H[6] * is;
+    rec.gy0 = g.H[1] * is;
+    rec.gy1 = g.H[4] * is;
+    rec.gy2 = g.H[7] * is;
+    rec.o = op;
+    rec.k2 = g.k2;
+    rec.ax = (int16_t)fp.q.ax;
+    rec.ay = (int16_t)fp.q.ay;
+}
+
 // Each workgroup first runs the view test on its kThreads surfels, then
 // packs the undecided ones into its first waves (in surfel order) so that
 // the double-precision path runs on full waves and the waves left without
 // a surfel end at once; every surfel still writes only its own outputs.
 // At least four waves per SIMD (128 VGPRs): the double-precision work is
-// latency-bound and needs the occupancy.
+// latency-bound and needs the occupancy.  EXT: the tile mode is LINEARISED
+// or the low-pass option is on (tiles from fs_sweep_tiles_ext / the widened
+// bounding box; the record's box covers the low-pass disc too).
+template <bool EXT>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
 preprocess_kernel(const float* __restrict__ means, const float* __restrict__ scales, const float* __restrict__ quats,
                   const float* __restrict__ opacity, int64_t n, const fs_camera* __restrict__ cams, fs_opts o,
@@ -62,7 +88,9 @@ preprocess_kernel(const float* __restrict__ means, const float* __restrict__ sca
     bool cand = false;
     if (i0 + tid < n) {
         const int64_t k = i0 + tid;
-        if (fs_outside_view(means + 3 * k, scales + 2 * k, opacity[k], cam, kmax))
+        // (the test bounds the exact footprint only: the linearised ellipse and
+        // the low-pass disc may reach further, so EXT runs every surfel)
+        if (!EXT && fs_outside_view(means + 3 * k, scales + 2 * k, opacity[k], cam, kmax))
             tiles_touched[(int64_t)v * n + k] = 0u;   // nothing else is written for a surfel without tiles
         else
             cand = true;
@@ -115,7 +143,40 @@ preprocess_kernel(const float* __restrict__ means, const float* __restrict__ sca
     };
     FsGeo g;
     const float op = opacity[i];
-    if (fs_project(means + 3 * i, scales + 2 * i, quats + 4 * i, op, cam, (double)o.alpha_min, g)) {
+    if (EXT && fs_project(means + 3 * i, scales + 2 * i, quats + 4 * i, op, cam, (double)o.alpha_min, g)) {
+        FsFootprint fp;
+        const bool exact_ok = fs_footprint(g, cam.width, cam.height, fp);
+        FsAssign a;
+        fs_assign_setup(g, fp, exact_ok, cam.width, cam.height, o.tile_mode == FS_TILES_LINEARISED, o.lowpass != 0, a);
+        const int S = o.tile;
+        if (o.tile_mode == FS_TILES_BBOX) {
+            int tx0, tx1, ty0, ty1;
+            if (fs_bbox_tiles_ext(fp, exact_ok, a, cam.width, cam.height, S, tx0, tx1, ty0, ty1)) {
+                const uint32_t nt = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+                bx = tx0;
+                by = ty0;
+                if (nt <= FS_INLINE_TILES) {
+                    for (int ty = ty0; ty <= ty1; ++ty)
+                        for (int tx = tx0; tx <= tx1; ++tx) note(tx, ty);
+                } else {
+                    count = nt;
+                }
+            }
+        } else if (a.have_ar) {
+            bx = a.ar[0] / S;
+            by = a.ar[2] / S;
+            fs_sweep_tiles_ext(fp, a, S, note);
+        }
+        if (count > 0) {
+            fs_fill_record(g, fp, op, rec);
+            if (a.have_box) {
+                rec.x0 = (int16_t)a.box[0];
+                rec.x1 = (int16_t)a.box[1];
+                rec.y0 = (int16_t)a.box[2];
+                rec.y1 = (int16_t)a.box[3];
+            }
+        }
+    } else if (!EXT && fs_project(means + 3 * i, scales + 2 * i, quats + 4 * i, op, cam, (double)o.alpha_min, g)) {
         FsFootprint fp;
         if (fs_footprint(g, cam.width, cam.height, fp)) {
             const int S = o.tile;
@@ -139,25 +200,7 @@ preprocess_kernel(const float* __restrict__ means, const float* __restrict__ sca
             }
         }
         if (count > 0) {
-            // render coefficients, anchored and normalised (h2 = 1 at the
-            // projected centre)
-            const double mx = g.T[2] / g.T[8], my = g.T[5] / g.T[8];
-            const double s = (g.H[6] * mx + g.H[7] * my) + g.H[8];
-            const double is = 1.0 / s;
-            const double xa = fp.q.ax + 0.5, ya = fp.q.ay + 0.5;
-            rec.h0 = ((g.H[0] * xa + g.H[1] * ya) + g.H[2]) * is;
-            rec.h1 = ((g.H[3] * xa + g.H[4] * ya) + g.H[5]) * is;
-            rec.h2 = ((g.H[6] * xa + g.H[7] * ya) + g.H[8]) * is;
-            rec.gx0 = g.H[0] * is;
-            rec.gx1 = g.H[3] * is;
-            rec.gx2 = g.H[6] * is;
-            rec.gy0 = g.H[1] * is;
-            rec.gy1 = g.H[4] * is;
-            rec.gy2 = g.H[7] * is;
-            rec.o = op;
-            rec.k2 = g.k2;
-            rec.ax = (int16_t)fp.q.ax;
-            rec.ay = (int16_t)fp.q.ay;
+            fs_fill_record(g, fp, op, rec);
             rec.x0 = (int16_t)fp.px0;
             rec.x1 = (int16_t)fp.px1;
             rec.y0 = (int16_t)fp.py0;
@@ -184,7 +227,9 @@ hipError_t fs_launch_preprocess(const float* means, const float* scales, const f
     dim3 grid((unsigned)((n + kThreads - 1) / kThreads), (unsigned)num_views);
     // bound on the cutoff radius k for opacities <= 1, widened against rounding
     const double kmax = std::sqrt(2.0 * std::log(1.0 / (double)o.alpha_min)) * (1.0 + 1e-9);
-    hipLaunchKernelGGL(preprocess_kernel, grid, dim3(kThreads), 0, s, means, scales, quats, opacity, n, cams, o,
-                       records, tiles_touched, reinterpret_cast<uint4*>(tile_cache), kmax);
+    const bool ext = o.tile_mode == FS_TILES_LINEARISED || o.lowpass != 0;
+    hipLaunchKernelGGL(ext ? preprocess_kernel<true> : preprocess_kernel<false>, grid, dim3(kThreads), 0, s, means,
+                       scales, quats, opacity, n, cams, o, records, tiles_touched,
+                       reinterpret_cast<uint4*>(tile_cache), kmax);
     return hipGetLastError();
 }

@@ -681,8 +681,8 @@ hipError_t fs_launch_render_backward(const float* means, const float* scales, co
     if (o.topk > 0 && o.topk <= kGradMaxK && C % ve == 0 && C / ve <= 64 && ws.topk_pairs != nullptr &&
         ws.topk_counts != nullptr && nblocks < (int64_t(1) << 31)) {
         // recompute the selection, then the per-block gradient pass
-        e = fs_launch_topk_select(records, vals, ranges, n, cams, num_views, total_tiles, o, nullptr, ws.topk_counts,
-                                  nullptr, nullptr, nullptr, ws, s);
+        e = fs_launch_topk_select(records, nullptr, vals, ranges, n, cams, num_views, total_tiles, o, nullptr,
+                                  ws.topk_counts, nullptr, nullptr, nullptr, nullptr, nullptr, ws, s);
         if (e != hipSuccess) return e;
         e = bf16 ? launch_topk_grad<uint16_t>(records, feats, C, n, cams, num_views, nblocks, o, grad_feat,
                                               grad_records, grad_feats, ws, s)

@@ -48,7 +48,7 @@ struct RowVec {
     static constexpr int kElems = VEC ? 16 / (int)sizeof(FT) : 1;
 };
 
-template <int CPL, typename FT, int WAVES, int BG>
+template <int CPL, typename FT, int WAVES, int BG, bool EXT>
 struct FwdShared {
     FsRecord rec[BG];
     uint32_t recid[BG];
@@ -58,16 +58,37 @@ struct FwdShared {
     int active;
     int list[BG];
     uint32_t item;
+    double2 mu[EXT ? BG : 1];    // low-pass: projected centre relative to the anchor
+    float4 geo[EXT ? BG : 1];    // depth and normal outputs: camera-facing normal, centre depth
 };
 
+// Per-entry data of the extended render (low-pass option, depth and normal
+// outputs), staged once per batch by the entry's own thread.
+FS_DEV void stage_ext(const FsRecord& r, const fs_camera& cam, const uint64_t* __restrict__ keys, uint32_t pos,
+                      bool lowpass, bool geo, double2& mu, float4& g) {
+    if (lowpass) {
+        double mx, my;
+        fs_record_centre(r, mx, my);
+        mu = make_double2(mx, my);
+    }
+    if (geo) {
+        const float3 nrm = fs_record_normal(r, cam);
+        // the centre depth is needed (and keys given) only for the depth output
+        g = make_float4(nrm.x, nrm.y, nrm.z, keys ? __uint_as_float((uint32_t)keys[pos]) : 0.f);
+    }
+}
+
 // One render block: the walk over its tile's list (see the file comment).
-template <int CPL, typename FT, int WAVES, int BG, bool VEC>
-FS_DEV void render_block(int64_t block, FwdShared<CPL, FT, WAVES, BG>& sm, const FsRecord* __restrict__ records,
-                         const uint32_t* __restrict__ vals, const uint32_t* __restrict__ ranges,
-                         const FT* __restrict__ feats, int C, int64_t n, int64_t num_records,
-                         const fs_camera* __restrict__ cams, int num_views, int S, const fs_opts& o,
-                         float* __restrict__ out_feat, float* __restrict__ out_T, int32_t* __restrict__ out_n,
-                         int32_t* __restrict__ out_last, int32_t* __restrict__ out_idx,
+// EXT: the low-pass response (o.lowpass) and the depth and normal outputs
+// (out_depth / out_normal, chunk 0 only) are available.
+template <int CPL, typename FT, int WAVES, int BG, bool VEC, bool EXT>
+FS_DEV void render_block(int64_t block, FwdShared<CPL, FT, WAVES, BG, EXT>& sm, const FsRecord* __restrict__ records,
+                         const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                         const uint32_t* __restrict__ ranges, const FT* __restrict__ feats, int C, int64_t n,
+                         int64_t num_records, const fs_camera* __restrict__ cams, int num_views, int S,
+                         const fs_opts& o, float* __restrict__ out_feat, float* __restrict__ out_T,
+                         int32_t* __restrict__ out_n, int32_t* __restrict__ out_last, int32_t* __restrict__ out_idx,
+                         float* __restrict__ out_depth, float* __restrict__ out_normal,
                          uint64_t* __restrict__ counters) {
     constexpr int NT = WAVES * 64;
     constexpr int kChunk = 64 * CPL;
@@ -90,6 +111,9 @@ FS_DEV void render_block(int64_t block, FwdShared<CPL, FT, WAVES, BG>& sm, const
     const uint32_t start = ranges[2 * bp.tile], end = ranges[2 * bp.tile + 1];
     const int K = o.topk;
     const bool write_idx = out_idx != nullptr && chunk == 0 && K > 0;
+    const bool lowpass = EXT && o.lowpass != 0;
+    const bool geo = EXT && chunk == 0 && (out_depth != nullptr || out_normal != nullptr);
+    float gD = 0.f, gN0 = 0.f, gN1 = 0.f, gN2 = 0.f;   // depth and normal sums
 
     double T = 1.0;
     int cnt = 0;
@@ -163,6 +187,11 @@ FS_DEV void render_block(int64_t block, FwdShared<CPL, FT, WAVES, BG>& sm, const
             fetch_records(nxt_rid);
             fetch_vals(b0 + 2 * BG, nxt_rid);
         }
+        if constexpr (EXT) {
+            if ((lowpass || geo) && tid < nb)
+                stage_ext(sm.rec[tid], cam, keys, b0 + (uint32_t)tid, lowpass, geo, sm.mu[tid], sm.geo[tid]);
+            __syncthreads();
+        }
         // 2. weights, lanes = pixels
         uint32_t mask = 0u;
         if (!__all(done)) {
@@ -170,7 +199,9 @@ FS_DEV void render_block(int64_t block, FwdShared<CPL, FT, WAVES, BG>& sm, const
                 const FsRecord& r = sm.rec[e];
                 if (r.x1 < wx0 || r.x0 > wx0 + 7 || r.y1 < wy0 || r.y0 > wy0 + 7) continue;
                 if (!done) {
-                    const FsResp rs = fs_response(r, (double)(px - r.ax), (double)(py - r.ay));
+                    FsResp rs = fs_response(r, (double)(px - r.ax), (double)(py - r.ay));
+                    if constexpr (EXT)
+                        if (lowpass) fs_lowpass_d2(rs, (double)(px - r.ax), (double)(py - r.ay), sm.mu[e].x, sm.mu[e].y);
                     if (rs.d2 <= r.k2 && fs_in_box(r, px, py)) {
                         const float G = __builtin_amdgcn_exp2f(neg_half_log2e * (float)rs.d2);
                         const float alpha = fminf(o.alpha_max, r.o * G);
@@ -178,7 +209,17 @@ FS_DEV void render_block(int64_t block, FwdShared<CPL, FT, WAVES, BG>& sm, const
                         if (Tn < t_stop) {
                             done = true;
                         } else {
-                            sm.w[wave][e][lane] = (float)((double)alpha * T);
+                            const float w = (float)((double)alpha * T);
+                            sm.w[wave][e][lane] = w;
+                            if constexpr (EXT) {
+                                if (geo) {
+                                    const float4 gg = sm.geo[e];
+                                    gD = fmaf(w, (float)((double)gg.w * rs.rh), gD);
+                                    gN0 = fmaf(w, gg.x, gN0);
+                                    gN1 = fmaf(w, gg.y, gN1);
+                                    gN2 = fmaf(w, gg.z, gN2);
+                                }
+                            }
                             mask |= 1u << e;
                             T = Tn;
                             if (write_idx) out_idx[pix * K + cnt] = (int32_t)sm.recid[e];
@@ -280,6 +321,14 @@ FS_DEV void render_block(int64_t block, FwdShared<CPL, FT, WAVES, BG>& sm, const
         if (out_last) out_last[pix] = last;
         if (write_idx)
             for (int j = cnt; j < K; ++j) out_idx[pix * K + j] = -1;
+        if constexpr (EXT) {
+            if (out_depth) out_depth[pix] = gD;
+            if (out_normal) {
+                out_normal[3 * pix] = gN0;
+                out_normal[3 * pix + 1] = gN1;
+                out_normal[3 * pix + 2] = gN2;
+            }
+        }
     }
     const int cl = lane * CPL;
 #pragma unroll
@@ -301,15 +350,16 @@ FS_DEV void render_block(int64_t block, FwdShared<CPL, FT, WAVES, BG>& sm, const
 // Grid launch (order == nullptr): workgroup b renders block b.  Persistent
 // launch: workgroups take positions of `order` (blocks sorted by list
 // length, longest first) from an atomic ticket until the queue is empty.
-template <int CPL, typename FT, int WAVES, int BG, bool VEC>
+template <int CPL, typename FT, int WAVES, int BG, bool VEC, bool EXT>
 __global__ void __launch_bounds__(WAVES * 64)
-render_fwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restrict__ vals,
-                  const uint32_t* __restrict__ ranges, const FT* __restrict__ feats, int C, int64_t n,
-                  int64_t num_records, const fs_camera* __restrict__ cams, int num_views, int S, fs_opts o,
-                  float* __restrict__ out_feat, float* __restrict__ out_T, int32_t* __restrict__ out_n,
-                  int32_t* __restrict__ out_last, int32_t* __restrict__ out_idx, uint64_t* __restrict__ counters,
+render_fwd_kernel(const FsRecord* __restrict__ records, const uint64_t* __restrict__ keys,
+                  const uint32_t* __restrict__ vals, const uint32_t* __restrict__ ranges, const FT* __restrict__ feats,
+                  int C, int64_t n, int64_t num_records, const fs_camera* __restrict__ cams, int num_views, int S,
+                  fs_opts o, float* __restrict__ out_feat, float* __restrict__ out_T, int32_t* __restrict__ out_n,
+                  int32_t* __restrict__ out_last, int32_t* __restrict__ out_idx, float* __restrict__ out_depth,
+                  float* __restrict__ out_normal, uint64_t* __restrict__ counters,
                   const uint32_t* __restrict__ order, uint32_t* __restrict__ ticket, uint32_t nblocks) {
-    __shared__ FwdShared<CPL, FT, WAVES, BG> sm;
+    __shared__ FwdShared<CPL, FT, WAVES, BG, EXT> sm;
     if (order == nullptr) {
         // the XCDs take one tile row of blocks each in turn: neighbouring
         // blocks share an L2 and dense regions are spread over all XCDs
@@ -317,8 +367,9 @@ render_fwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
         constexpr int RBv = WAVES == 1 ? 8 : 16;
         const int64_t tiles_x = ((int64_t)cams[0].width + S - 1) / S, sb = S / RBv;
         const int64_t blk = xcd_remap_chunked(blockIdx.x, gridDim.x, tiles_x * sb * sb);
-        render_block<CPL, FT, WAVES, BG, VEC>(blk, sm, records, vals, ranges, feats, C, n, num_records, cams,
-                                              num_views, S, o, out_feat, out_T, out_n, out_last, out_idx, counters);
+        render_block<CPL, FT, WAVES, BG, VEC, EXT>(blk, sm, records, keys, vals, ranges, feats, C, n, num_records,
+                                                   cams, num_views, S, o, out_feat, out_T, out_n, out_last, out_idx,
+                                                   out_depth, out_normal, counters);
         return;
     }
     for (;;) {
@@ -327,8 +378,9 @@ render_fwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
         __syncthreads();
         const uint32_t it = sm.item;
         if (it >= nblocks) break;
-        render_block<CPL, FT, WAVES, BG, VEC>(order[it], sm, records, vals, ranges, feats, C, n, num_records, cams,
-                                              num_views, S, o, out_feat, out_T, out_n, out_last, out_idx, counters);
+        render_block<CPL, FT, WAVES, BG, VEC, EXT>(order[it], sm, records, keys, vals, ranges, feats, C, n,
+                                                   num_records, cams, num_views, S, o, out_feat, out_T, out_n,
+                                                   out_last, out_idx, out_depth, out_normal, counters);
     }
 }
 
@@ -405,18 +457,19 @@ int device_cus() {
 }
 
 
-template <int CPL, typename FT, int WAVES, int BG>
-hipError_t launch(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges, const void* feats, int C,
-                  int64_t n, const fs_camera* cams, int num_views, int64_t total_tiles, const fs_opts& o,
-                  float* out_feat, float* out_T, int32_t* out_n, int32_t* out_last, int32_t* out_idx,
-                  uint64_t* counters, const FsWorkspace& ws, hipStream_t s) {
+template <int CPL, typename FT, int WAVES, int BG, bool EXT>
+hipError_t launch(const FsRecord* records, const uint64_t* keys, const uint32_t* vals, const uint32_t* ranges,
+                  const void* feats, int C, int64_t n, const fs_camera* cams, int num_views, int64_t total_tiles,
+                  const fs_opts& o, float* out_feat, float* out_T, int32_t* out_n, int32_t* out_last,
+                  int32_t* out_idx, float* out_depth, float* out_normal, uint64_t* counters, const FsWorkspace& ws,
+                  hipStream_t s) {
     constexpr int RB = WAVES == 1 ? 8 : 16;
     const int sb = o.tile / RB;
     const int64_t blocks = total_tiles * sb * sb;
     if (blocks >= (int64_t(1) << 32)) return hipErrorInvalidValue;
     const int chunks = (C + 64 * CPL - 1) / (64 * CPL);
     const bool vec = (C % (16 / (int)sizeof(FT))) == 0;
-    auto kern = vec ? render_fwd_kernel<CPL, FT, WAVES, BG, true> : render_fwd_kernel<CPL, FT, WAVES, BG, false>;
+    auto kern = vec ? render_fwd_kernel<CPL, FT, WAVES, BG, true, EXT> : render_fwd_kernel<CPL, FT, WAVES, BG, false, EXT>;
     if (o.schedule == FS_SCHED_PERSISTENT && chunks == 1 && blocks <= ws.render_max_blocks) {
         const uint32_t nb = (uint32_t)blocks;
         const hipError_t e = fs_launch_block_order(ranges, sb * sb, nb, ws, s);
@@ -427,34 +480,46 @@ hipError_t launch(const FsRecord* records, const uint32_t* vals, const uint32_t*
             per_cu = 1;
         int64_t grid = (int64_t)device_cus() * per_cu;
         if (grid > blocks) grid = blocks;
-        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(WAVES * 64), 0, s, records, vals, ranges,
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(WAVES * 64), 0, s, records, keys, vals, ranges,
                            static_cast<const FT*>(feats), C, n, n * num_views, cams, num_views, o.tile, o, out_feat,
-                           out_T, out_n, out_last, out_idx, counters, ws.render_order, ws.render_ticket, nb);
+                           out_T, out_n, out_last, out_idx, out_depth, out_normal, counters, ws.render_order,
+                           ws.render_ticket, nb);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks, (unsigned)chunks), dim3(WAVES * 64), 0, s, records, vals, ranges,
-                       static_cast<const FT*>(feats), C, n, n * num_views, cams, num_views, o.tile, o, out_feat,
-                       out_T, out_n, out_last, out_idx, counters, (const uint32_t*)nullptr, (uint32_t*)nullptr, 0u);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks, (unsigned)chunks), dim3(WAVES * 64), 0, s, records, keys, vals,
+                       ranges, static_cast<const FT*>(feats), C, n, n * num_views, cams, num_views, o.tile, o,
+                       out_feat, out_T, out_n, out_last, out_idx, out_depth, out_normal, counters,
+                       (const uint32_t*)nullptr, (uint32_t*)nullptr, 0u);
     return hipGetLastError();
 }
 
 template <int CPL, typename FT>
-hipError_t launch_waves(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges, const void* feats,
-                        int C, int64_t n, const fs_camera* cams, int num_views, int64_t total_tiles,
-                        const fs_opts& o, float* out_feat, float* out_T, int32_t* out_n, int32_t* out_last,
-                        int32_t* out_idx, uint64_t* counters, const FsWorkspace& ws, hipStream_t s) {
+hipError_t launch_waves(const FsRecord* records, const uint64_t* keys, const uint32_t* vals, const uint32_t* ranges,
+                        const void* feats, int C, int64_t n, const fs_camera* cams, int num_views,
+                        int64_t total_tiles, const fs_opts& o, float* out_feat, float* out_T, int32_t* out_n,
+                        int32_t* out_last, int32_t* out_idx, float* out_depth, float* out_normal,
+                        uint64_t* counters, const FsWorkspace& ws, hipStream_t s) {
     // 8x8 tiles: one-wave blocks; larger tiles: 16x16 blocks of four waves sharing the list staging
     const bool small = o.tile == 8;
     const bool bg16 = o.batch == 16;
-#define FS_LAUNCH(W, B)                                                                                          \
-    return launch<CPL, FT, W, B>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o, out_feat, \
-                                 out_T, out_n, out_last, out_idx, counters, ws, s)
-    if (small) {
-        if (bg16) FS_LAUNCH(1, 16);
-        FS_LAUNCH(1, 32);
+    // the low-pass response and the depth / normal outputs run in their own
+    // instantiations (32-entry batches), so the plain render carries none of
+    // their registers
+    const bool ext = o.lowpass != 0 || out_depth != nullptr || out_normal != nullptr;
+#define FS_LAUNCH(W, B, X)                                                                                         \
+    return launch<CPL, FT, W, B, X>(records, keys, vals, ranges, feats, C, n, cams, num_views, total_tiles, o,     \
+                                    out_feat, out_T, out_n, out_last, out_idx, out_depth, out_normal, counters, ws, \
+                                    s)
+    if (ext) {
+        if (small) FS_LAUNCH(1, 32, true);
+        FS_LAUNCH(4, 32, true);
     }
-    if (bg16) FS_LAUNCH(4, 16);
-    FS_LAUNCH(4, 32);
+    if (small) {
+        if (bg16) FS_LAUNCH(1, 16, false);
+        FS_LAUNCH(1, 32, false);
+    }
+    if (bg16) FS_LAUNCH(4, 16, false);
+    FS_LAUNCH(4, 32, false);
 #undef FS_LAUNCH
 }
 
@@ -474,20 +539,22 @@ hipError_t fs_launch_block_order(const uint32_t* ranges, int sb2, uint32_t nbloc
     return hipGetLastError();
 }
 
-hipError_t fs_launch_render_forward(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges,
-                                    const void* feats, int C, int64_t n, const fs_camera* cams, int num_views,
-                                    int64_t total_tiles, const fs_opts& o, float* out_feat, float* out_T,
-                                    int32_t* out_n, int32_t* out_last, int32_t* out_idx, uint64_t* counters,
+hipError_t fs_launch_render_forward(const FsRecord* records, const uint64_t* keys, const uint32_t* vals,
+                                    const uint32_t* ranges, const void* feats, int C, int64_t n,
+                                    const fs_camera* cams, int num_views, int64_t total_tiles, const fs_opts& o,
+                                    float* out_feat, float* out_T, int32_t* out_n, int32_t* out_last,
+                                    int32_t* out_idx, float* out_depth, float* out_normal, uint64_t* counters,
                                     const FsWorkspace& ws, hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
     const bool bf16 = o.feat_dtype == FS_FEAT_BF16;
-    if (C <= 64)
-        return bf16 ? launch_waves<1, uint16_t>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o,
-                                                out_feat, out_T, out_n, out_last, out_idx, counters, ws, s)
-                    : launch_waves<1, float>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o,
-                                             out_feat, out_T, out_n, out_last, out_idx, counters, ws, s);
-    return bf16 ? launch_waves<2, uint16_t>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o,
-                                            out_feat, out_T, out_n, out_last, out_idx, counters, ws, s)
-                : launch_waves<2, float>(records, vals, ranges, feats, C, n, cams, num_views, total_tiles, o,
-                                         out_feat, out_T, out_n, out_last, out_idx, counters, ws, s);
+#define FS_WAVES(CPLv, FTv)                                                                                          \
+    return launch_waves<CPLv, FTv>(records, keys, vals, ranges, feats, C, n, cams, num_views, total_tiles, o,      \
+                                   out_feat, out_T, out_n, out_last, out_idx, out_depth, out_normal, counters, ws, s)
+    if (C <= 64) {
+        if (bf16) FS_WAVES(1, uint16_t);
+        FS_WAVES(1, float);
+    }
+    if (bf16) FS_WAVES(2, uint16_t);
+    FS_WAVES(2, float);
+#undef FS_WAVES
 }

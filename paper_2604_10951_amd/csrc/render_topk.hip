@@ -37,7 +37,7 @@ static_assert(kStagedK <= kCompactK, "the staged gather reads compact lists");
 
 // KC > 0: every pixel's list (at most KC pairs) is kept in LDS during the
 // walk and written compactly at the end; KC = 0: lists written in place.
-template <int KC, bool BYW>
+template <int KC, bool BYW, bool EXT>
 struct SelShared {
     FsRecord rec[kSelBatch];
     uint32_t recid[kSelBatch];
@@ -47,6 +47,8 @@ struct SelShared {
     uint32_t mask[64];             // per pixel: entries of the batch it accepts
     uint2 list[64 * (KC > 0 ? KC : 1)];   // per pixel: (batch entry, then row slot; weight)
     uint32_t uniq[BYW ? 64 * KC : 1];     // by weight: the block's distinct selected records
+    double2 mu[EXT ? kSelBatch : 1];      // low-pass: projected centre relative to the anchor
+    float4 geo[EXT ? kSelBatch : 1];      // depth and normal outputs: camera-facing normal, centre depth
 };
 
 // List layout in the workspace, per 8x8 block b (region b * 64 * K of the
@@ -58,19 +60,23 @@ struct SelShared {
 // far (list position, weight).  After the walk the block's distinct selected
 // list positions are sorted and numbered: they are its row list, in list
 // order as in the first-K mode, and every pair's position becomes its slot.
-template <int KC, bool BYW>
+// EXT (first K only): the low-pass response (o.lowpass) and the depth and
+// normal outputs, summed with the weights the lists hold.
+template <int KC, bool BYW, bool EXT>
 __global__ void __launch_bounds__(64)
-topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restrict__ vals,
-                   const uint32_t* __restrict__ ranges, uint32_t n, int64_t num_records,
-                   const fs_camera* __restrict__ cams, int num_views, int S, fs_opts o, int64_t nblocks,
-                   uint2* __restrict__ pairs, uint32_t* __restrict__ rows,
+topk_select_kernel(const FsRecord* __restrict__ records, const uint64_t* __restrict__ keys,
+                   const uint32_t* __restrict__ vals, const uint32_t* __restrict__ ranges, uint32_t n,
+                   int64_t num_records, const fs_camera* __restrict__ cams, int num_views, int S, fs_opts o,
+                   int64_t nblocks, uint2* __restrict__ pairs, uint32_t* __restrict__ rows,
                    uint32_t* __restrict__ nrows, float* __restrict__ out_T, int32_t* __restrict__ out_n,
-                   int32_t* __restrict__ out_last, int32_t* __restrict__ out_idx, uint64_t* __restrict__ counters) {
+                   int32_t* __restrict__ out_last, int32_t* __restrict__ out_idx, float* __restrict__ out_depth,
+                   float* __restrict__ out_normal, uint64_t* __restrict__ counters) {
     constexpr int BG = kSelBatch;
     constexpr int kQ = FS_RECORD_BYTES / 16;          // float4 per record
     constexpr int kRecSlots = (BG * kQ + 63) / 64;    // record float4 per lane
     static_assert(!BYW || KC > 0, "the by-weight lists live in LDS");
-    __shared__ SelShared<KC, BYW> sm;
+    static_assert(!(BYW && EXT), "no extended outputs for the by-weight selection");
+    __shared__ SelShared<KC, BYW, EXT> sm;
     const int lane = threadIdx.x;
     const int64_t block = xcd_remap_chunked(blockIdx.x, nblocks, block_row_chunk(cams, S));
     const BlockPos bp = locate_block(block, S, 8, cams, num_views);
@@ -92,6 +98,9 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
     const float neg_half_log2e = -0.72134752044448170f;   // -log2(e) / 2
     uint32_t walked = 0;
     uint32_t nslots = 0;   // rows of the block's row list so far
+    const bool lowpass = EXT && o.lowpass != 0;
+    const bool geo = EXT && (out_depth != nullptr || out_normal != nullptr);
+    float gD = 0.f, gN0 = 0.f, gN1 = 0.f, gN2 = 0.f;   // depth and normal sums
 
     // list values of batch b + 2 and records of batch b + 1 are in flight
     // while batch b is walked
@@ -161,6 +170,19 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
         uint64_t epix = 0ull;
         if (lane < nb) {
             const FsRecord& r = sm.rec[lane];
+            if constexpr (EXT) {
+                if (lowpass) {
+                    double mx, my;
+                    fs_record_centre(r, mx, my);
+                    sm.mu[lane] = make_double2(mx, my);
+                }
+                if (geo) {
+                    const float3 nrm = fs_record_normal(r, cam);
+                    // the centre depth is needed (and keys given) only for the depth output
+                    sm.geo[lane] = make_float4(nrm.x, nrm.y, nrm.z,
+                                               keys ? __uint_as_float((uint32_t)keys[b0 + lane]) : 0.f);
+                }
+            }
             const int x0 = max((int)r.x0, bp.x0), x1 = min((int)r.x1, bp.x0 + 7);
             const int y0 = max((int)r.y0, bp.y0), y1 = min((int)r.y1, bp.y0 + 7);
             if (x0 <= x1 && y0 <= y1) {
@@ -206,7 +228,10 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
                 }
                 const int lx = p & 7, ly = p >> 3;
                 const FsRecord& r = sm.rec[e];
-                const FsResp rs = fs_response(r, (double)(bp.x0 + lx - r.ax), (double)(bp.y0 + ly - r.ay));
+                const double ddx = (double)(bp.x0 + lx - r.ax), ddy = (double)(bp.y0 + ly - r.ay);
+                FsResp rs = fs_response(r, ddx, ddy);
+                if constexpr (EXT)
+                    if (lowpass) fs_lowpass_d2(rs, ddx, ddy, sm.mu[e].x, sm.mu[e].y);
                 if (rs.d2 <= r.k2) atomicOr(&sm.mask[p], 1u << e);
             }
         }
@@ -220,16 +245,24 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
         uint32_t bm = 0u;
         const int c_start = cnt;
         const double T_start = T;
-        auto alpha_of = [&](int e) {
+        auto resp_of = [&](int e) {
             const FsRecord& r = sm.rec[e];
-            const FsResp rs = fs_response(r, (double)(px - r.ax), (double)(py - r.ay));
-            const float G = __builtin_amdgcn_exp2f(neg_half_log2e * (float)rs.d2);
-            return fminf(o.alpha_max, r.o * G);
+            const double ddx = (double)(px - r.ax), ddy = (double)(py - r.ay);
+            FsResp rs = fs_response(r, ddx, ddy);
+            if constexpr (EXT)
+                if (lowpass) fs_lowpass_d2(rs, ddx, ddy, sm.mu[e].x, sm.mu[e].y);
+            return rs;
         };
+        auto alpha_from = [&](int e, const FsResp& rs) {
+            const float G = __builtin_amdgcn_exp2f(neg_half_log2e * (float)rs.d2);
+            return fminf(o.alpha_max, sm.rec[e].o * G);
+        };
+        auto alpha_of = [&](int e) { return alpha_from(e, resp_of(e)); };
         while (hit != 0u && !done) {
             const int e = __builtin_ctz(hit);
             hit &= hit - 1u;
-            const float al = alpha_of(e);
+            const FsResp rs = resp_of(e);
+            const float al = alpha_from(e, rs);
             const double Tn = T * (1.0 - (double)al);
             if (Tn < t_stop) {
                 done = true;
@@ -263,6 +296,16 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
                 if constexpr (KC > 0) {
                     sm.list[lane * KC + cnt] = make_uint2((uint32_t)e, __float_as_uint((float)((double)al * T)));
                     if (out_idx) out_idx[pix * K + cnt] = (int32_t)sm.recid[e];
+                }
+                if constexpr (EXT) {
+                    if (geo) {
+                        const float w = (float)((double)al * T);
+                        const float4 gg = sm.geo[e];
+                        gD = fmaf(w, (float)((double)gg.w * rs.rh), gD);
+                        gN0 = fmaf(w, gg.x, gN0);
+                        gN1 = fmaf(w, gg.y, gN1);
+                        gN2 = fmaf(w, gg.z, gN2);
+                    }
                 }
                 T = Tn;
                 ++cnt;
@@ -394,6 +437,14 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint32_t* __restr
         if (out_last) out_last[pix] = last;
         if (out_idx)
             for (int j = cnt; j < K; ++j) out_idx[pix * K + j] = -1;
+        if constexpr (EXT) {
+            if (out_depth) out_depth[pix] = gD;
+            if (out_normal) {
+                out_normal[3 * pix] = gN0;
+                out_normal[3 * pix + 1] = gN1;
+                out_normal[3 * pix + 2] = gN2;
+            }
+        }
     }
 }
 
@@ -760,31 +811,39 @@ hipError_t launch_gather(const uint2* pairs, const int32_t* counts, const uint32
 
 }  // namespace
 
-hipError_t fs_launch_topk_select(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges, int64_t n,
-                                 const fs_camera* cams, int num_views, int64_t total_tiles, const fs_opts& o,
-                                 float* out_T, int32_t* out_n, int32_t* out_last, int32_t* out_idx,
+hipError_t fs_launch_topk_select(const FsRecord* records, const uint64_t* keys, const uint32_t* vals,
+                                 const uint32_t* ranges, int64_t n, const fs_camera* cams, int num_views,
+                                 int64_t total_tiles, const fs_opts& o, float* out_T, int32_t* out_n,
+                                 int32_t* out_last, int32_t* out_idx, float* out_depth, float* out_normal,
                                  uint64_t* counters, const FsWorkspace& ws, hipStream_t s) {
     const int sb = o.tile / 8;
     const int64_t nblocks = total_tiles * sb * sb;
     if (ws.topk_pairs == nullptr || ws.topk_rows == nullptr || ws.topk_nrows == nullptr ||
         ws.topk_pair_slots < nblocks * 64 * (int64_t)o.topk || nblocks >= (int64_t(1) << 31))
         return hipErrorInvalidValue;
+    const bool ext = o.lowpass != 0 || out_depth != nullptr || out_normal != nullptr;
+    if (ext && o.topk_mode == FS_TOPK_WEIGHT) return hipErrorInvalidValue;
     auto kern = o.topk_mode == FS_TOPK_WEIGHT
-                    ? (o.topk <= 8 ? topk_select_kernel<8, true> : topk_select_kernel<kCompactK, true>)
-                    : (o.topk <= 8 ? topk_select_kernel<8, false>
-                                   : (o.topk <= kCompactK ? topk_select_kernel<kCompactK, false>
-                                                          : topk_select_kernel<0, false>));
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(64), 0, s, records, vals, ranges, (uint32_t)n,
+                    ? (o.topk <= 8 ? topk_select_kernel<8, true, false> : topk_select_kernel<kCompactK, true, false>)
+                : ext ? (o.topk <= 8 ? topk_select_kernel<8, false, true>
+                                     : (o.topk <= kCompactK ? topk_select_kernel<kCompactK, false, true>
+                                                            : topk_select_kernel<0, false, true>))
+                      : (o.topk <= 8 ? topk_select_kernel<8, false, false>
+                                     : (o.topk <= kCompactK ? topk_select_kernel<kCompactK, false, false>
+                                                            : topk_select_kernel<0, false, false>));
+    hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(64), 0, s, records, keys, vals, ranges, (uint32_t)n,
                        n * num_views, cams, num_views, o.tile, o, nblocks, ws.topk_pairs, ws.topk_rows,
-                       ws.topk_nrows, out_T, out_n, out_last, out_idx, counters);
+                       ws.topk_nrows, out_T, out_n, out_last, out_idx, out_depth, out_normal, counters);
     return hipGetLastError();
 }
 
-hipError_t fs_launch_render_topk_split(const FsRecord* records, const uint32_t* vals, const uint32_t* ranges,
-                                       const void* feats, int C, int64_t n, const fs_camera* cams, int num_views,
-                                       int64_t total_tiles, const fs_opts& o, float* out_feat, int32_t* out_label,
-                                       float* out_score, float* out_T, int32_t* out_n, int32_t* out_last,
-                                       int32_t* out_idx, uint64_t* counters, const FsWorkspace& ws, hipStream_t s) {
+hipError_t fs_launch_render_topk_split(const FsRecord* records, const uint64_t* keys, const uint32_t* vals,
+                                       const uint32_t* ranges, const void* feats, int C, int64_t n,
+                                       const fs_camera* cams, int num_views, int64_t total_tiles, const fs_opts& o,
+                                       float* out_feat, int32_t* out_label, float* out_score, float* out_T,
+                                       int32_t* out_n, int32_t* out_last, int32_t* out_idx, float* out_depth,
+                                       float* out_normal, uint64_t* counters, const FsWorkspace& ws,
+                                       hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
     const int sb = o.tile / 8;
     const int64_t nblocks = total_tiles * sb * sb;
@@ -792,8 +851,8 @@ hipError_t fs_launch_render_topk_split(const FsRecord* records, const uint32_t* 
         ws.topk_pair_slots < nblocks * 64 * (int64_t)o.topk || nblocks >= (int64_t(1) << 31) ||
         (out_feat == nullptr) == (out_label == nullptr))
         return hipErrorInvalidValue;
-    hipError_t e = fs_launch_topk_select(records, vals, ranges, n, cams, num_views, total_tiles, o, out_T, out_n,
-                                         out_last, out_idx, counters, ws, s);
+    hipError_t e = fs_launch_topk_select(records, keys, vals, ranges, n, cams, num_views, total_tiles, o, out_T,
+                                         out_n, out_last, out_idx, out_depth, out_normal, counters, ws, s);
     if (e != hipSuccess) return e;
     const bool bf16 = o.feat_dtype == FS_FEAT_BF16;
     const bool vec = C % (bf16 ? 8 : 4) == 0;

@@ -54,6 +54,8 @@ class Frame:
     vals: torch.Tensor
     ranges: torch.Tensor        # (total_tiles, 2)
     generation: int = -1        # which fill of the rasterizer's shared buffers the frame read
+    depth: torch.Tensor | None = None    # (total_pixels,) sum of w z (intersection depths)
+    normal: torch.Tensor | None = None   # (total_pixels, 3) sum of w n (camera-space normals)
 
     def view_image(self, rast: "Rasterizer", v: int = 0, what: str = "feat") -> torch.Tensor:
         cam = rast.cam_arr[v]
@@ -68,19 +70,19 @@ class Rasterizer:
     def __init__(self, cams, *, tile: int = 16, topk: int = 0, tile_mode: str = "precise",
                  feat_dtype: str = "f32", alpha_min: float = ALPHA_MIN, alpha_max: float = ALPHA_MAX,
                  t_stop: float = T_STOP, batch: int = 0, schedule: str = "auto", topk_mode: str = "first",
-                 device: str | torch.device = "cuda", pair_capacity: int = 0):
+                 lowpass: bool = False, device: str | torch.device = "cuda", pair_capacity: int = 0):
         self.lib = L.load()
         self.device = torch.device(device)
         self.cams = list(cams) if isinstance(cams, (list, tuple)) else [cams]
         self.num_views = len(self.cams)
-        mode = {"precise": L.FS_TILES_PRECISE, "bbox": L.FS_TILES_BBOX}[tile_mode]
+        mode = {"precise": L.FS_TILES_PRECISE, "bbox": L.FS_TILES_BBOX, "linearised": L.FS_TILES_LINEARISED}[tile_mode]
         dt = {"f32": L.FS_FEAT_F32, "bf16": L.FS_FEAT_BF16}[feat_dtype]
         self.feat_dtype = feat_dtype
         if schedule == "auto":   # the measured fastest: split for Top-K, the fused grid for the full blend
             schedule = "split" if topk > 0 else "grid"
         sched = {"grid": L.FS_SCHED_GRID, "persistent": L.FS_SCHED_PERSISTENT, "split": L.FS_SCHED_SPLIT}[schedule]
         kmode = {"first": L.FS_TOPK_FIRST, "weight": L.FS_TOPK_WEIGHT}[topk_mode]
-        self.opts = L.make_opts(tile, topk, mode, dt, alpha_min, alpha_max, t_stop, batch, sched, kmode)
+        self.opts = L.make_opts(tile, topk, mode, dt, alpha_min, alpha_max, t_stop, batch, sched, kmode, int(lowpass))
         self.cam_arr, self.total_tiles, self.total_pixels = L.make_cameras(self.cams, tile)
         raw = bytes(ctypes.string_at(ctypes.addressof(self.cam_arr), ctypes.sizeof(self.cam_arr)))
         self.cams_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(self.device)
@@ -160,25 +162,21 @@ class Rasterizer:
         return b["ranges"]
 
     def render_forward(self, feats, *, out=None, want_last: bool = False, want_idx: bool = False,
-                       counters: torch.Tensor | None = None):
+                       want_depth: bool = False, want_normal: bool = False, counters: torch.Tensor | None = None):
         n, C = feats.shape
         if feats.dtype != (torch.bfloat16 if self.feat_dtype == "bf16" else torch.float32) or not feats.is_contiguous():
             raise ValueError(f"feats must be contiguous {self.feat_dtype}")
         b = self._bufs
         dev = self.device
         if out is None:
-            out = {
-                "feat": torch.empty((self.total_pixels, C), dtype=torch.float32, device=dev),
-                "T": torch.empty(self.total_pixels, dtype=torch.float32, device=dev),
-                "n": torch.empty(self.total_pixels, dtype=torch.int32, device=dev),
-                "last": torch.empty(self.total_pixels, dtype=torch.int32, device=dev) if want_last else None,
-                "idx": (torch.empty((self.total_pixels, self.topk), dtype=torch.int32, device=dev)
-                        if want_idx and self.topk > 0 else None),
-            }
-        L.check(self.lib.fs_render_forward(_p(b["records"]), _p(b["vals"]), _p(b["ranges"]), _p(feats), C, n,
-                                           _p(self.cams_dev), self.num_views, self.total_tiles,
-                                           ctypes.byref(self.opts), _p(out["feat"]), _p(out["T"]), _p(out["n"]),
-                                           _p(out["last"]), _p(out["idx"]), _p(counters), _p(b["ws"]), _stream(dev)),
+            out = self.alloc_out(C, want_last=want_last, want_idx=want_idx, want_depth=want_depth,
+                                 want_normal=want_normal)
+        depth, normal = out.get("depth"), out.get("normal")
+        L.check(self.lib.fs_render_forward(_p(b["records"]), _p(b["keys"]) if depth is not None else None,
+                                           _p(b["vals"]), _p(b["ranges"]), _p(feats), C, n, _p(self.cams_dev),
+                                           self.num_views, self.total_tiles, ctypes.byref(self.opts), _p(out["feat"]),
+                                           _p(out["T"]), _p(out["n"]), _p(out["last"]), _p(out["idx"]), _p(depth),
+                                           _p(normal), _p(counters), _p(b["ws"]), _stream(dev)),
                 "fs_render_forward")
         return out
 
@@ -205,7 +203,7 @@ class Rasterizer:
         return out
 
     def render(self, means, scales, quats, opacity, feats, *, want_last: bool = False,
-               want_idx: bool = False) -> Frame:
+               want_idx: bool = False, want_depth: bool = False, want_normal: bool = False) -> Frame:
         n = means.shape[0]
         _f32(means, (n, 3), "means")
         _f32(scales, (n, 2), "scales")
@@ -214,10 +212,12 @@ class Rasterizer:
         self.preprocess(means, scales, quats, opacity)
         P = self.bin(means, scales, quats, opacity)
         self.sort(P)
-        out = self.render_forward(feats, want_last=want_last, want_idx=want_idx)
+        out = self.render_forward(feats, want_last=want_last, want_idx=want_idx, want_depth=want_depth,
+                                  want_normal=want_normal)
         b = self._bufs
         return Frame(out["feat"], out["T"], out["n"], out["last"], out["idx"], P, b["records"], b["tiles"],
-                     b["keys"], b["vals"], b["ranges"].view(self.total_tiles, 2), self.generation)
+                     b["keys"], b["vals"], b["ranges"].view(self.total_tiles, 2), self.generation, out.get("depth"),
+                     out.get("normal"))
 
     def render_nosync(self, means, scales, quats, opacity, feats, out: dict, counters=None, events=None) -> None:
         """All four stages without any host synchronisation (the pair count
@@ -257,7 +257,8 @@ class Rasterizer:
     def pairs_fit(self) -> bool:
         return int(self._bufs["num_pairs"].item()) <= self.capacity
 
-    def alloc_out(self, C: int, want_last: bool = False, want_idx: bool = False) -> dict:
+    def alloc_out(self, C: int, want_last: bool = False, want_idx: bool = False, want_depth: bool = False,
+                  want_normal: bool = False) -> dict:
         dev = self.device
         return {
             "feat": torch.empty((self.total_pixels, C), dtype=torch.float32, device=dev),
@@ -266,6 +267,8 @@ class Rasterizer:
             "last": torch.empty(self.total_pixels, dtype=torch.int32, device=dev) if want_last else None,
             "idx": (torch.empty((self.total_pixels, self.topk), dtype=torch.int32, device=dev)
                     if want_idx and self.topk > 0 else None),
+            "depth": torch.empty(self.total_pixels, dtype=torch.float32, device=dev) if want_depth else None,
+            "normal": torch.empty((self.total_pixels, 3), dtype=torch.float32, device=dev) if want_normal else None,
         }
 
     def alloc_labels(self, want_score: bool = True) -> dict:

@@ -75,21 +75,22 @@ def check_image(fr, ref, rast, v, C, K, name, *, pixels=None):
     return {"max_rel_err": worst, "masked": masked, "pixels": int(ok.size)}
 
 
-def check_pairs(fr, scene, cams, tile):
-    """Tile counts, sorted keys/values and ranges bit-exact against the oracle."""
+def check_pairs(fr, scene, cams, tile, mode="precise", lowpass=False):
+    """Tile counts, sorted keys/values and ranges bit-exact against the oracle
+    (tile assignment `mode` of the oracle, with or without the low-pass disc)."""
     cams = cams if isinstance(cams, (list, tuple)) else [cams]
     n = scene.n
     counts_gpu = fr.tiles_touched.cpu().numpy().astype(np.uint32)
     flagged = np.zeros(len(cams) * n, bool)
     for v, cam in enumerate(cams):
         proj = oracle.project_scene(scene, cam)
-        counts, flags, _, _ = oracle.tile_sets(proj, cam.width, cam.height, tile)
+        counts, flags, _, _ = oracle.tile_sets(proj, cam.width, cam.height, tile, mode=mode, lowpass=lowpass)
         sl = slice(v * n, (v + 1) * n)
         flagged[sl] = flags != 0
         assert np.array_equal(counts_gpu[sl][flags == 0], counts[flags == 0]), \
             f"view {v}: tile counts differ for {(counts_gpu[sl] != counts).sum()} surfels"
     assert flagged.sum() == 0, f"{flagged.sum()} surfels decided within 1e-12 of the cutoff"
-    keys, vals, ntiles = oracle.sorted_pairs(scene, cams, tile)
+    keys, vals, ntiles = oracle.sorted_pairs(scene, cams, tile, mode=mode, lowpass=lowpass)
     P = fr.num_pairs
     assert P == keys.shape[0]
     gk = fr.keys[:P].cpu().numpy().view(np.uint64)
