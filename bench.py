@@ -124,7 +124,7 @@ def _time_frames(rast, tens, steps, warmup):
     return a.elapsed_time(b) / steps
 
 
-def _plain(cams, tens, dev, steps, warmup, topk=0, tile=8, schedule="grid"):
+def _plain(cams, tens, dev, steps, warmup, topk=0, tile=8, schedule="persistent"):
     """Plain FP32 full blend (the comparison point of every form)."""
     rast = raster.Rasterizer(cams, tile=tile, topk=topk, schedule=schedule, device=dev)
     rast.render(*tens)
@@ -268,7 +268,7 @@ def form_ablation(scene_tens, dev, steps, warmup):
             rows[name]["pixels_differing_from_D"] = int(((fr.T != ref_T["T"]) | (fr.n != ref_T["n"])).sum().item())
         del rast, fr
         torch.cuda.empty_cache()
-    return {"workload": "1M surfels, 1280x720, C=128, 8x8 tiles; full blend: fused grid schedule, Top-K K=8: split; "
+    return {"workload": "1M surfels, 1280x720, C=128, 8x8 tiles; full blend: fused longest-first schedule, Top-K K=8: split; "
                         "row E: the linearised Sigma' tile assignment of Sec. 3.2 read literally",
             "tiles": int((1280 // 8) * (720 // 8)), "rows": rows}
 
@@ -477,7 +477,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tile", type=int, default=TILE)
     ap.add_argument("--schedule", default="split", choices=("grid", "persistent", "split"),
-                    help="render schedule of the Top-K frames (the full blend uses 'grid')")
+                    help="render schedule of the Top-K frames (the full blend uses 'persistent')")
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16 / batched / backward forms")
     ap.add_argument("--form", choices=("batched", "backward", "bf16", "topk_weight", "labels", "ablation"), default=None,
                     help="run only this form and print its JSON line (profiling)")
@@ -522,7 +522,7 @@ def main():
 
     results = {}
     for name, topk in (("topk", K), ("topk16", 16), ("full", 0)):
-        rast = raster.Rasterizer(cam, tile=args.tile, topk=topk, schedule=args.schedule if topk else "grid",
+        rast = raster.Rasterizer(cam, tile=args.tile, topk=topk, schedule=args.schedule if topk else "persistent",
                                  device=dev)
         counts = frame_counts(rast, tens, C)   # also establishes the pair capacity
         out = rast.alloc_out(C)

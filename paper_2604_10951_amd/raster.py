@@ -78,8 +78,8 @@ class Rasterizer:
         mode = {"precise": L.FS_TILES_PRECISE, "bbox": L.FS_TILES_BBOX, "linearised": L.FS_TILES_LINEARISED}[tile_mode]
         dt = {"f32": L.FS_FEAT_F32, "bf16": L.FS_FEAT_BF16}[feat_dtype]
         self.feat_dtype = feat_dtype
-        if schedule == "auto":   # the measured fastest: split for Top-K, the fused grid for the full blend
-            schedule = "split" if topk > 0 else "grid"
+        if schedule == "auto":   # the measured fastest: split for Top-K, the longest-first queue for the full blend
+            schedule = "split" if topk > 0 else "persistent"
         sched = {"grid": L.FS_SCHED_GRID, "persistent": L.FS_SCHED_PERSISTENT, "split": L.FS_SCHED_SPLIT}[schedule]
         kmode = {"first": L.FS_TOPK_FIRST, "weight": L.FS_TOPK_WEIGHT}[topk_mode]
         self.opts = L.make_opts(tile, topk, mode, dt, alpha_min, alpha_max, t_stop, batch, sched, kmode, int(lowpass))
