@@ -6,8 +6,9 @@
 // the 64-bit key gives, since a record is emitted at most once per tile and
 // records are emitted in increasing order.  It is produced in two steps that
 // suit a list split into many short per-tile runs:
-//   1. a counting sort by tile: per-tile counts (LDS histograms per 8192-pair
-//      chunk), one exclusive scan that also yields every tile's [start, end)
+//   1. a counting sort by tile: per-tile counts (LDS histograms over the tile
+//      window of each 8192-pair chunk), one exclusive scan that also yields
+//      every tile's [start, end)
 //      range, and a scatter that places each pair at its tile's start plus a
 //      cursor (any order inside the tile);
 //   2. a sort of every tile's run by (depth key, record), as 64-bit composite
@@ -54,36 +55,77 @@ __global__ void sort_clear_kernel(uint32_t* __restrict__ cnt, uint32_t* __restri
     if (blockIdx.x == 0 && threadIdx.x < 2) ticket[threadIdx.x] = 0;   // scan ticket, long-run count
 }
 
-// Per-tile counts.  With at most kLdsTiles tiles every workgroup counts a
-// contiguous chunk of pairs in an LDS histogram and adds its non-zero bins to
-// the global counts, so a tile with many pairs costs one global atomic per
-// workgroup, not one per pair; with more tiles, pairs are counted with
-// global atomics.
+// Tile window of a chunk of pairs: [lo, hi] over its valid tile ids (lo >
+// hi when it has none), reduced over the workgroup.  Pairs are emitted
+// record by record and records view by view, so a chunk's tiles lie within
+// one view (two where it straddles a boundary): the window of a view with at
+// most kLdsTiles tiles fits the LDS histograms below whatever the total.
+FS_DEV void chunk_window(const uint64_t* __restrict__ keys, int64_t c0, int64_t c1, int64_t tiles, uint32_t& lo,
+                         uint32_t& hi, uint32_t* s_red) {
+    uint32_t a = 0xffffffffu, b = 0u;
+    for (int64_t i = c0 + threadIdx.x; i < c1; i += kChunkThreads) {
+        const uint64_t t = keys[i] >> 32;
+        if (t < (uint64_t)tiles) {
+            a = (uint32_t)t < a ? (uint32_t)t : a;
+            b = (uint32_t)t > b ? (uint32_t)t : b;
+        }
+    }
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t x = __shfl_xor(a, d, 64), y = __shfl_xor(b, d, 64);
+        a = x < a ? x : a;
+        b = y > b ? y : b;
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        s_red[2 * wave] = a;
+        s_red[2 * wave + 1] = b;
+    }
+    __syncthreads();
+    lo = 0xffffffffu;
+    hi = 0u;
+    for (int w = 0; w < kChunkThreads / 64; ++w) {
+        lo = s_red[2 * w] < lo ? s_red[2 * w] : lo;
+        hi = s_red[2 * w + 1] > hi ? s_red[2 * w + 1] : hi;
+    }
+}
+
+// Per-tile counts.  Every workgroup counts a chunk of kChunk pairs: in an LDS
+// histogram over the chunk's tile window when it spans at most kLdsTiles
+// tiles, adding its non-zero bins to the global counts (a tile with many
+// pairs costs one global atomic per workgroup, not one per pair); with global
+// atomics per pair otherwise.
 __global__ void __launch_bounds__(kChunkThreads)
 sort_count_kernel(const uint64_t* __restrict__ keys, const int64_t* __restrict__ num_pairs, int64_t capacity,
                   int64_t tiles, uint32_t* __restrict__ cnt) {
     __shared__ uint32_t h[kLdsTiles];
+    __shared__ uint32_t s_red[2 * (kChunkThreads / 64)];
     const int64_t P = load_count(num_pairs, capacity);
+    const int64_t c0 = (int64_t)blockIdx.x * kChunk;
+    if (c0 >= P) return;   // uniform across the workgroup
+    const int64_t c1 = c0 + kChunk < P ? c0 + kChunk : P;
+    uint32_t lo = 0u, hi = (uint32_t)(tiles - 1);   // all tiles fit: no window needed
     if (tiles > kLdsTiles) {
-        const int64_t stride = (int64_t)gridDim.x * kChunkThreads;
-        for (int64_t i = (int64_t)blockIdx.x * kChunkThreads + threadIdx.x; i < P; i += stride) {
+        chunk_window(keys, c0, c1, tiles, lo, hi, s_red);
+        if (hi < lo) return;
+    }
+    const uint32_t W = hi - lo + 1u;
+    if (W > (uint32_t)kLdsTiles) {
+        for (int64_t i = c0 + threadIdx.x; i < c1; i += kChunkThreads) {
             const uint64_t t = keys[i] >> 32;
             if (t < (uint64_t)tiles) atomicAdd(&cnt[t], 1u);
         }
         return;
     }
-    const int T = (int)tiles;
-    for (int i = threadIdx.x; i < T; i += kChunkThreads) h[i] = 0;
+    for (uint32_t i = threadIdx.x; i < W; i += kChunkThreads) h[i] = 0;
     __syncthreads();
-    const int64_t c0 = (int64_t)blockIdx.x * kChunk;
-    const int64_t c1 = c0 + kChunk < P ? c0 + kChunk : P;
     for (int64_t i = c0 + threadIdx.x; i < c1; i += kChunkThreads) {
         const uint64_t t = keys[i] >> 32;
-        if (t < (uint64_t)tiles) atomicAdd(&h[t], 1u);
+        if (t < (uint64_t)tiles) atomicAdd(&h[(uint32_t)t - lo], 1u);
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < T; i += kChunkThreads)
-        if (h[i]) atomicAdd(&cnt[i], h[i]);
+    for (uint32_t i = threadIdx.x; i < W; i += kChunkThreads)
+        if (h[i]) atomicAdd(&cnt[lo + i], h[i]);
 }
 
 FS_DEV uint32_t wave_inclusive_scan(uint32_t x) {
@@ -174,18 +216,28 @@ sort_scan_kernel(const uint32_t* __restrict__ cnt, int64_t tiles, uint32_t* __re
 }
 
 // Pair i goes to its tile's start plus a cursor, as (depth key, record).
-// With at most kLdsTiles tiles every workgroup reserves, per tile, one run of
-// positions for its whole chunk (one global atomic per tile it touches) and
-// hands them out with LDS cursors; otherwise every pair takes a global atomic.
+// Per chunk, as in the count: over an LDS window of at most kLdsTiles tiles
+// the workgroup reserves, per tile, one run of positions for its whole chunk
+// (one global atomic per tile it touches) and hands them out with LDS
+// cursors; otherwise every pair takes a global atomic.
 __global__ void __launch_bounds__(kChunkThreads)
 sort_scatter_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
                     const int64_t* __restrict__ num_pairs, int64_t capacity, int64_t tiles,
                     const uint32_t* __restrict__ ranges, uint32_t* __restrict__ fill, uint2* __restrict__ out) {
     __shared__ uint32_t h[kLdsTiles];
+    __shared__ uint32_t s_red[2 * (kChunkThreads / 64)];
     const int64_t P = load_count(num_pairs, capacity);
+    const int64_t c0 = (int64_t)blockIdx.x * kChunk;
+    if (c0 >= P) return;   // uniform across the workgroup
+    const int64_t c1 = c0 + kChunk < P ? c0 + kChunk : P;
+    uint32_t lo = 0u, hi = (uint32_t)(tiles - 1);   // all tiles fit: no window needed
     if (tiles > kLdsTiles) {
-        const int64_t stride = (int64_t)gridDim.x * kChunkThreads;
-        for (int64_t i = (int64_t)blockIdx.x * kChunkThreads + threadIdx.x; i < P; i += stride) {
+        chunk_window(keys, c0, c1, tiles, lo, hi, s_red);
+        if (hi < lo) return;
+    }
+    const uint32_t W = hi - lo + 1u;
+    if (W > (uint32_t)kLdsTiles) {
+        for (int64_t i = c0 + threadIdx.x; i < c1; i += kChunkThreads) {
             const uint64_t k = keys[i];
             const uint64_t t = k >> 32;
             if (t < (uint64_t)tiles) {
@@ -195,14 +247,11 @@ sort_scatter_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restric
         }
         return;
     }
-    const int T = (int)tiles;
-    for (int i = threadIdx.x; i < T; i += kChunkThreads) h[i] = 0;
+    for (uint32_t i = threadIdx.x; i < W; i += kChunkThreads) h[i] = 0;
     __syncthreads();
-    const int64_t c0 = (int64_t)blockIdx.x * kChunk;
-    const int64_t c1 = c0 + kChunk < P ? c0 + kChunk : P;
     for (int64_t i = c0 + threadIdx.x; i < c1; i += kChunkThreads) {
         const uint64_t t = keys[i] >> 32;
-        if (t < (uint64_t)tiles) atomicAdd(&h[t], 1u);
+        if (t < (uint64_t)tiles) atomicAdd(&h[(uint32_t)t - lo], 1u);
     }
     __syncthreads();
     // first position of this chunk's run in every tile it touches: the
@@ -213,24 +262,24 @@ sort_scatter_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restric
     uint32_t cnt[kRounds], got[kRounds], first[kRounds];
 #pragma unroll
     for (int k = 0; k < kRounds; ++k) {
-        const int i = (int)threadIdx.x + k * kChunkThreads;
-        cnt[k] = i < T ? h[i] : 0u;
+        const uint32_t i = threadIdx.x + (uint32_t)k * kChunkThreads;
+        cnt[k] = i < W ? h[i] : 0u;
         got[k] = 0u;
         first[k] = 0u;
         if (cnt[k] != 0u) {
-            got[k] = atomicAdd(&fill[i], cnt[k]);
-            first[k] = ranges[2 * i];
+            got[k] = atomicAdd(&fill[lo + i], cnt[k]);
+            first[k] = ranges[2 * (lo + i)];
         }
     }
 #pragma unroll
     for (int k = 0; k < kRounds; ++k)
-        if (cnt[k] != 0u) h[(int)threadIdx.x + k * kChunkThreads] = first[k] + got[k];
+        if (cnt[k] != 0u) h[threadIdx.x + k * kChunkThreads] = first[k] + got[k];
     __syncthreads();
     for (int64_t i = c0 + threadIdx.x; i < c1; i += kChunkThreads) {
         const uint64_t k = keys[i];
         const uint64_t t = k >> 32;
         if (t < (uint64_t)tiles) {
-            const uint32_t pos = atomicAdd(&h[t], 1u);
+            const uint32_t pos = atomicAdd(&h[(uint32_t)t - lo], 1u);
             if ((int64_t)pos < P) out[pos] = make_uint2((uint32_t)k, vals[i]);
         }
     }
@@ -520,15 +569,9 @@ hipError_t fs_launch_sort(uint64_t* keys, uint32_t* vals, int64_t capacity, cons
         hipLaunchKernelGGL(sort_clear_kernel, dim3(blocks), dim3(256), 0, s, ws.tile_cnt, ws.tile_fill, total_tiles,
                            ws.sort_status, parts, ws.sort_ticket);
     }
-    unsigned pblocks;
-    if (total_tiles <= kLdsTiles) {
-        const int64_t chunks = (pmax + kChunk - 1) / kChunk;
-        if (chunks >= (int64_t(1) << 31)) return hipErrorInvalidValue;
-        pblocks = (unsigned)(chunks < 1 ? 1 : chunks);
-    } else {
-        const int64_t b = (pmax + kChunkThreads * 4 - 1) / (kChunkThreads * 4);
-        pblocks = (unsigned)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
-    }
+    const int64_t chunks = (pmax + kChunk - 1) / kChunk;
+    if (chunks >= (int64_t(1) << 31)) return hipErrorInvalidValue;
+    const unsigned pblocks = (unsigned)(chunks < 1 ? 1 : chunks);
     hipLaunchKernelGGL(sort_count_kernel, dim3(pblocks), dim3(kChunkThreads), 0, s, keys, num_pairs, capacity,
                        total_tiles, ws.tile_cnt);
     hipLaunchKernelGGL(sort_scan_kernel, dim3((unsigned)parts), dim3(kThreads), 0, s, ws.tile_cnt, total_tiles, ranges,
