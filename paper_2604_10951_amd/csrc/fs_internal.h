@@ -155,10 +155,8 @@ FS_DEV bool fs_project(const float* pm, const float* ps, const float* pq, float 
     return true;
 }
 
-// The footprint predicate at pixel (px, py): u^2 + v^2 <= k^2 with
-// (u, v) = (h0 / h2, h1 / h2), h = H (px + .5, py + .5, 1).
-// 1/x and sqrt(x) (x >= 0) to ~1e-15 relative: hardware seeds plus Newton
-// steps (each step doubles the bits of the ~2^-23 seeds).
+// 1/x to ~1e-15 relative: the hardware seed (~2^-23) refined by two Newton
+// steps (each doubles its bits).
 FS_DEV double fs_rcp_approx(double x) {
     double r = __builtin_amdgcn_rcp(x);
     r = fma(r, fma(-x, r, 1.0), r);
@@ -166,16 +164,17 @@ FS_DEV double fs_rcp_approx(double x) {
     return r;
 }
 
-FS_DEV double fs_sqrt_approx(double x) {
+// sqrt(x) (x >= 0) to ~1e-13 relative: the reciprocal square root seed
+// (~2^-23) after one Newton step, times x.
+FS_DEV double fs_sqrt_line(double x) {
     if (!(x > 0.0)) return 0.0;
-    double y = __builtin_amdgcn_rsq(x);      // 1 / sqrt(x)
+    double y = __builtin_amdgcn_rsq(x);
     y = y * fma(-0.5 * x * y, y, 1.5);
-    y = y * fma(-0.5 * x * y, y, 1.5);
-    double r = x * y;                        // sqrt(x)
-    r = fma(0.5 * y, fma(-r, r, x), r);      // one Newton step on r
-    return r;
+    return x * y;
 }
 
+// The footprint predicate at pixel (px, py): u^2 + v^2 <= k^2 with
+// (u, v) = (h0 / h2, h1 / h2), h = H (px + .5, py + .5, 1).
 FS_DEV bool fs_pixel_in(const double H[9], double k2, int px, int py) {
     const double x = (double)px + 0.5, y = (double)py + 0.5;
     const double h0 = (H[0] * x + H[1] * y) + H[2];
@@ -328,21 +327,16 @@ FS_DEV bool fs_conic_line(const FsConic& q, Pin&& pin, bool rows, int l, int lo_
         return true;
     }
     // The roots only locate the interval: every centre within eps of a root
-    // is re-decided below with the exact predicate, so they need ~1e-15
-    // relative accuracy, not correct rounding -- hardware reciprocal and
-    // reciprocal square root seeds refined by Newton steps.
-    const double sq = fs_sqrt_approx(disc);
-    // roots s1 <= s2 (numerically stable form)
-    double s1, s2;
-    if (b >= 0.0) {
-        const double t = -(b + sq);
-        s1 = t * fs_rcp_approx(a);
-        s2 = (t != 0.0) ? c * fs_rcp_approx(t) : 0.0;
-    } else {
-        const double t = -b + sq;
-        s2 = t * fs_rcp_approx(a);
-        s1 = c * fs_rcp_approx(t);
-    }
+    // is re-decided below with the exact predicate, so they need an absolute
+    // error far below eps, not correct rounding.  (-b -+ sqrt(disc)) / a with
+    // 1/a (the same for every line of the footprint) and sqrt(disc) from
+    // hardware seeds refined by Newton steps: the relative error of sqrt is
+    // ~1e-13, and the cancellation in -b + sqrt(disc) leaves an absolute
+    // error of a few ulps of |b| / a, so for |s| <= 4e6 every root is within
+    // 1e-6 px.
+    const double sq = fs_sqrt_line(disc);
+    const double ra = fs_rcp_approx(a);
+    double s1 = (-b - sq) * ra, s2 = (-b + sq) * ra;
     if (s1 > s2) {
         const double tmp = s1;
         s1 = s2;

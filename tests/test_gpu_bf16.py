@@ -75,8 +75,12 @@ def test_precision_workload_sampled(dtype):
     feats = _bf16_round(scene.feats) if dtype == "bf16" else scene.feats
     ref = oracle.render_pixels(proj, scene.opacity, feats, cam.width, pix, K=16)
     check_image(fr, ref, rast, 0, 256, 16, f"C=256 {dtype}", pixels=pix)
+    # error of each output against the FP64 oracle on the float32 features
+    ref_f = ref if dtype == "f32" else oracle.render_pixels(proj, scene.opacity, scene.feats, cam.width, pix, K=16)
+    mx, mean = _stats(fr, ref_f, rast, 256, pixels=pix)
+    Tg = fr.view_image(rast, 0, "T").cpu().numpy().reshape(-1)[pix]
+    eT = np.abs(Tg.astype(np.float64) - ref_f.T.reshape(-1))
+    print(f"{dtype} C=256 K=16 vs oracle(f32 features): features max {mx:.3g} mean {mean:.3g} (relative to "
+          f"sum w|c|); T max {eT.max():.3g} mean {eT.mean():.3g} (absolute)", flush=True)
     if dtype == "bf16":
-        ref_f = oracle.render_pixels(proj, scene.opacity, scene.feats, cam.width, pix, K=16)
-        mx, mean = _stats(fr, ref_f, rast, 256, pixels=pix)
-        print(f"bf16 C=256 vs oracle(f32 features): max {mx:.3g} mean {mean:.3g}", flush=True)
         assert mx <= BF16_BOUND
