@@ -378,18 +378,40 @@ FS_DEV bool fs_line_interval(const FsFootprint& fp, bool rows, int l, int lo_lim
 // row in row mode, a tile column in column mode) the tile spans of its pixel
 // lines are OR-ed into a 64-bit mask over a window of at most 64 tiles, then
 // visit(tx, ty) is called for each tile of the union, in increasing order.
+// The lines of a tile line are visited from the one nearest the conic's
+// centre outwards, and the visit stops once the mask holds every tile of the
+// candidate range in the window: no further line can add a tile, so the
+// union is unchanged (a footprint within one tile column usually needs a
+// single line solve per tile line).
 template <class Visit>
 FS_DEV void fs_sweep_tiles(const FsFootprint& fp, int S, Visit&& visit) {
     const bool rows = (fp.py1 - fp.py0) <= (fp.px1 - fp.px0);
     const int l0 = rows ? fp.py0 : fp.px0, l1 = rows ? fp.py1 : fp.px1;      // lines
     const int s0 = rows ? fp.px0 : fp.py0, s1 = rows ? fp.px1 : fp.py1;      // along-line range
     const int ts0 = s0 / S, ts1 = s1 / S;
+    // the line through the conic's centre (the middle of the range if the
+    // conic is not a bounded ellipse)
+    int lc = (l0 + l1) >> 1;
+    {
+        const FsConic& q = fp.q;
+        const double det = q.A * q.C - q.B * q.B;
+        if (q.A > 0.0 && q.C > 0.0 && det > 0.0) {
+            const double cen = rows ? (q.B * q.D - q.A * q.E) / det + (double)q.ay
+                                    : (q.B * q.E - q.C * q.D) / det + (double)q.ax;
+            if (cen > (double)l0 && cen < (double)l1) lc = (int)rint(cen);
+        }
+    }
     for (int wbase = ts0; wbase <= ts1; wbase += 64) {
+        const int f1 = ts1 - wbase < 63 ? ts1 - wbase : 63;
+        const uint64_t full = f1 == 63 ? ~0ull : ((1ull << (f1 + 1)) - 1ull);   // bits ts0 - wbase (= 0) .. f1
         for (int tl = l0 / S; tl <= l1 / S; ++tl) {
             uint64_t mask = 0;
             const int la = tl * S > l0 ? tl * S : l0;
             const int lb = tl * S + S - 1 < l1 ? tl * S + S - 1 : l1;
-            for (int l = la; l <= lb; ++l) {
+            const int lm = lc < la ? la : (lc > lb ? lb : lc);
+            for (int k = 0; k <= lb - la && mask != full; ++k) {
+                // lm, lm + 1, .., lb, then lm - 1, .., la
+                const int l = lm + k <= lb ? lm + k : lm - (k - (lb - lm));
                 int lo, hi;
                 if (!fs_line_interval(fp, rows, l, s0, s1, lo, hi)) continue;
                 int t1 = lo / S - wbase, t2 = hi / S - wbase;
