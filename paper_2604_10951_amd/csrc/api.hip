@@ -81,7 +81,7 @@ bool fs_workspace_layout(void* base, int64_t n, int32_t num_views, int64_t total
     const size_t sort_bytes = align_up(off, 256);
     // render stage: work queue of render blocks (at most 16 per tile: 8x8 blocks of a 32x32 tile)
     off = 0;
-    w.render_ticket = static_cast<uint32_t*>(take(sizeof(uint32_t) * 16));
+    w.render_ticket = static_cast<uint32_t*>(take(sizeof(uint32_t) * kRenderQueues * kTicketStride));
     w.render_hist = static_cast<uint32_t*>(take(sizeof(uint32_t) * 64));
     w.render_offs = static_cast<uint32_t*>(take(sizeof(uint32_t) * 64));
     w.render_max_blocks = (total_tiles > 0 ? total_tiles : 1) * 16;

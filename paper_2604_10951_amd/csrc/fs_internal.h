@@ -898,7 +898,7 @@ struct FsWorkspace {
     uint2* runs;             // pairs grouped by tile, (depth key, record), capacity entries
     uint32_t* long_list;     // tiles whose runs are longer than one wave sorts
     // render
-    uint32_t* render_ticket;
+    uint32_t* render_ticket;   // kRenderQueues tickets, kTicketStride words apart
     uint32_t* render_hist;
     uint32_t* render_offs;
     uint32_t* render_order;
@@ -940,8 +940,16 @@ hipError_t fs_launch_render_forward(const FsRecord* records, const uint64_t* key
                                     int32_t* out_idx, float* out_depth, float* out_normal, uint64_t* counters,
                                     const FsWorkspace& ws, hipStream_t s);
 
+// Work queues of the persistent render and the spacing of their tickets
+// (256 B apart).  A ticket is a memory-side atomic, serialised per address:
+// one ticket for every item of the frame limited the full blend (0.39 ms,
+// against 0.336 ms with 8 queues and 0.332 ms with 32).
+constexpr uint32_t kRenderQueues = 32;
+constexpr uint32_t kTicketStride = 64;
+
 // Work order of render blocks (tile list length, longest first; ties in any
-// order) into ws.render_order; zeroes ws.render_ticket.
+// order) into ws.render_order; zeroes the kRenderQueues tickets of
+// ws.render_ticket.
 hipError_t fs_launch_block_order(const uint32_t* ranges, int sb2, uint32_t nblocks, const FsWorkspace& ws,
                                  hipStream_t s);
 

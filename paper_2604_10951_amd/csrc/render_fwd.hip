@@ -349,7 +349,7 @@ FS_DEV void render_block(int64_t block, FwdShared<CPL, FT, WAVES, BG, EXT>& sm, 
 
 // Grid launch (order == nullptr): workgroup b renders block b.  Persistent
 // launch: workgroups take positions of `order` (blocks sorted by list
-// length, longest first) from an atomic ticket until the queue is empty.
+// length, longest first) from atomic tickets until the queues are empty.
 template <int CPL, typename FT, int WAVES, int BG, bool VEC, bool EXT>
 __global__ void __launch_bounds__(WAVES * 64)
 render_fwd_kernel(const FsRecord* __restrict__ records, const uint64_t* __restrict__ keys,
@@ -372,11 +372,13 @@ render_fwd_kernel(const FsRecord* __restrict__ records, const uint64_t* __restri
                                                    out_depth, out_normal, counters);
         return;
     }
+    const uint32_t nq = gridDim.x < kRenderQueues ? gridDim.x : kRenderQueues;   // as in render_wide_kernel
+    const uint32_t q = blockIdx.x % nq;
     for (;;) {
         __syncthreads();   // every wave is done with the previous item (and sm.item)
-        if (threadIdx.x == 0) sm.item = atomicAdd(ticket, 1u);
+        if (threadIdx.x == 0) sm.item = atomicAdd(ticket + q * kTicketStride, 1u);
         __syncthreads();
-        const uint32_t it = sm.item;
+        const uint32_t it = sm.item * nq + q;
         if (it >= nblocks) break;
         render_block<CPL, FT, WAVES, BG, VEC, EXT>(order[it], sm, records, keys, vals, ranges, feats, C, n,
                                                    num_records, cams, num_views, S, o, out_feat, out_T, out_n,
@@ -797,11 +799,16 @@ render_wide_kernel(const FsRecord* __restrict__ records, const uint64_t* __restr
                                                      out_idx, out_depth, out_normal, counters);
         return;
     }
+    // nq queues: workgroup g takes items q, q + nq, q + 2 nq, .. (q = g mod
+    // nq) from a ticket of its own, so the tickets (memory-side atomics,
+    // each serialised per address) are shared by a grid's nq-th part only
+    const uint32_t nq = gridDim.x < kRenderQueues ? gridDim.x : kRenderQueues;
+    const uint32_t q = blockIdx.x % nq;
     for (;;) {
         __syncthreads();   // every wave is done with the previous item (and sm.item)
-        if (threadIdx.x == 0) sm.item = atomicAdd(ticket, 1u);
+        if (threadIdx.x == 0) sm.item = atomicAdd(ticket + q * kTicketStride, 1u);
         __syncthreads();
-        const uint32_t it = sm.item;
+        const uint32_t it = sm.item * nq + q;
         if (it >= nblocks) break;
         render_block_wide<CPL, FT, NW, BG, VEC, EXT>(order[it], sm, records, keys, vals, ranges, feats, C, n,
                                                      num_records, cams, num_views, S, o, out_feat, out_T, out_n,
@@ -829,7 +836,7 @@ __global__ void order_hist_kernel(const uint32_t* __restrict__ ranges, int sb2, 
     }
     __syncthreads();
     if (threadIdx.x < 64 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
-    if (b == 0) *ticket = 0u;
+    if (b < kRenderQueues) ticket[b * kTicketStride] = 0u;
 }
 
 __global__ void order_scan_kernel(uint32_t* __restrict__ hist, uint32_t* __restrict__ offs) {
