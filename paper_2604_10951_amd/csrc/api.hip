@@ -86,6 +86,8 @@ bool fs_workspace_layout(void* base, int64_t n, int32_t num_views, int64_t total
     w.render_offs = static_cast<uint32_t*>(take(sizeof(uint32_t) * 64));
     w.render_max_blocks = (total_tiles > 0 ? total_tiles : 1) * 16;
     w.render_order = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)w.render_max_blocks));
+    w.sel_long = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)w.render_max_blocks));
+    w.sel_counts = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)((w.render_max_blocks + 255) / 256)));
     if (opts && opts->topk > 0) {
         // Top-K lists: the split forward and the Top-K backward
         const int64_t sb = opts->tile / 8;

@@ -903,6 +903,8 @@ struct FsWorkspace {
     uint32_t* render_offs;
     uint32_t* render_order;
     int64_t render_max_blocks;
+    uint32_t* sel_long;     // split Top-K selection: long-list blocks, per 256-block group
+    uint32_t* sel_counts;   // their number per group
     // split Top-K render: (row slot, weight bits) of the first K blended
     // surfels of every pixel, indexed [8x8 block][pixel of block][k]; the
     // surfel index of every row slot of a block, [8x8 block][slot]; and the

@@ -28,6 +28,8 @@
 namespace {
 
 constexpr int kSelBatch = 32;   // list entries staged per step in the selection pass
+constexpr uint32_t kSelLong = 48;   // blocks with longer tile lists are selected first
+constexpr int kSelGroup = 256;       // blocks per group of the long-block list
 constexpr int kGatherThreads = 256;
 constexpr int kGatherUnroll = 8;  // (surfel, weight) pairs whose row loads are in flight together
 constexpr int kStagedK = 16;      // largest K of the staged gather (its lists live in LDS)
@@ -51,6 +53,68 @@ struct SelShared {
     float4 geo[EXT ? kSelBatch : 1];      // depth and normal outputs: camera-facing normal, centre depth
 };
 
+// The blocks whose tile list holds more than kSelLong entries, per group of
+// kSelGroup consecutive blocks: their indices at long[g * kSelGroup ..] and
+// their number at counts[g].  No atomics and nothing to clear beforehand.
+__global__ void __launch_bounds__(kSelGroup)
+select_long_kernel(const uint32_t* __restrict__ ranges, int sb2, int64_t nblocks, uint32_t* __restrict__ lng,
+                   uint32_t* __restrict__ counts) {
+    __shared__ uint32_t s_wave[kSelGroup / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t b = (int64_t)blockIdx.x * kSelGroup + tid;
+    bool is_long = false;
+    if (b < nblocks) {
+        const int64_t t = b / sb2;
+        is_long = ranges[2 * t + 1] - ranges[2 * t] > kSelLong;
+    }
+    const uint64_t m = __ballot(is_long);
+    if (lane == 0) s_wave[wave] = (uint32_t)__popcll(m);
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kSelGroup / 64; ++w) {
+        before += w < wave ? s_wave[w] : 0u;
+        total += s_wave[w];
+    }
+    if (is_long) lng[(int64_t)blockIdx.x * kSelGroup + before + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)b;
+    if (tid == 0) counts[blockIdx.x] = total;
+}
+
+// Block of a selection workgroup.  The first nblocks workgroups (dispatched
+// first) take the long-list blocks, the i-th of them the i-th long block;
+// the others take every block in grid order and skip the long ones.  Returns
+// -1 for a workgroup without a block.
+FS_DEV int64_t select_block_of(int64_t nblocks, const fs_camera* cams, int S, int sb2, const uint32_t* ranges,
+                               const uint32_t* lng, const uint32_t* counts) {
+    const int lane = threadIdx.x & 63;
+    const int64_t g = blockIdx.x;
+    if (g >= nblocks) {
+        const int64_t b = xcd_remap_chunked(g - nblocks, nblocks, block_row_chunk(cams, S));
+        const int64_t t = b / sb2;
+        return ranges[2 * t + 1] - ranges[2 * t] > kSelLong ? -1 : b;
+    }
+    // the group holding long block g: running sum of the groups' counts
+    const int64_t ngroups = (nblocks + kSelGroup - 1) / kSelGroup;
+    uint32_t run = 0;
+    for (int64_t c0 = 0; c0 < ngroups; c0 += 64) {
+        const uint32_t c = c0 + lane < ngroups ? counts[c0 + lane] : 0u;
+        uint32_t incl = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += y;
+        }
+        const uint64_t past = __ballot((int64_t)(run + incl) > g);
+        if (past) {
+            const int l = __builtin_ctzll(past);
+            const uint32_t excl = run + __shfl(incl, l, 64) - __shfl(c, l, 64);
+            return lng[(c0 + l) * kSelGroup + (g - excl)];
+        }
+        run += __shfl(incl, 63, 64);
+    }
+    return -1;   // fewer long blocks than g + 1
+}
+
 // List layout in the workspace, per 8x8 block b (region b * 64 * K of the
 // pair array): with KC > 0 the pairs of pixel p start at the sum of the
 // counts of pixels 0 .. p - 1 (compact), and nrows[b] = rows | pairs << 16;
@@ -70,7 +134,8 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint64_t* __restr
                    int64_t nblocks, uint2* __restrict__ pairs, uint32_t* __restrict__ rows,
                    uint32_t* __restrict__ nrows, float* __restrict__ out_T, int32_t* __restrict__ out_n,
                    int32_t* __restrict__ out_last, int32_t* __restrict__ out_idx, float* __restrict__ out_depth,
-                   float* __restrict__ out_normal, uint64_t* __restrict__ counters) {
+                   float* __restrict__ out_normal, uint64_t* __restrict__ counters,
+                   const uint32_t* __restrict__ lng, const uint32_t* __restrict__ lcounts) {
     constexpr int BG = kSelBatch;
     constexpr int kQ = FS_RECORD_BYTES / 16;          // float4 per record
     constexpr int kRecSlots = (BG * kQ + 63) / 64;    // record float4 per lane
@@ -78,9 +143,11 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint64_t* __restr
     static_assert(!(BYW && EXT), "no extended outputs for the by-weight selection");
     __shared__ SelShared<KC, BYW, EXT> sm;
     const int lane = threadIdx.x;
-    const int64_t block = xcd_remap_chunked(blockIdx.x, nblocks, block_row_chunk(cams, S));
+    const int sb2 = (S / 8) * (S / 8);
+    const int64_t block = select_block_of(nblocks, cams, S, sb2, ranges, lng, lcounts);
+    if (block < 0) return;   // uniform across the wave
     const BlockPos bp = locate_block(block, S, 8, cams, num_views);
-    if (!bp.valid) return;   // uniform across the wave
+    if (!bp.valid) return;
     const fs_camera& cam = cams[bp.view];
     const int px = bp.x0 + (lane & 7), py = bp.y0 + (lane >> 3);
     const bool inside = px < cam.width && py < cam.height;
@@ -831,9 +898,17 @@ hipError_t fs_launch_topk_select(const FsRecord* records, const uint64_t* keys, 
                       : (o.topk <= 8 ? topk_select_kernel<8, false, false>
                                      : (o.topk <= kCompactK ? topk_select_kernel<kCompactK, false, false>
                                                             : topk_select_kernel<0, false, false>));
-    hipLaunchKernelGGL(kern, dim3((unsigned)nblocks), dim3(64), 0, s, records, keys, vals, ranges, (uint32_t)n,
+    // long-list blocks first: their list, then nblocks workgroups for them and
+    // nblocks for the grid order
+    if (ws.sel_long == nullptr || ws.sel_counts == nullptr || nblocks > ws.render_max_blocks ||
+        2 * nblocks >= (int64_t(1) << 31))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(select_long_kernel, dim3((unsigned)((nblocks + kSelGroup - 1) / kSelGroup)), dim3(kSelGroup), 0,
+                       s, ranges, sb * sb, nblocks, ws.sel_long, ws.sel_counts);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(2 * nblocks)), dim3(64), 0, s, records, keys, vals, ranges, (uint32_t)n,
                        n * num_views, cams, num_views, o.tile, o, nblocks, ws.topk_pairs, ws.topk_rows,
-                       ws.topk_nrows, out_T, out_n, out_last, out_idx, out_depth, out_normal, counters);
+                       ws.topk_nrows, out_T, out_n, out_last, out_idx, out_depth, out_normal, counters, ws.sel_long,
+                       ws.sel_counts);
     return hipGetLastError();
 }
 
