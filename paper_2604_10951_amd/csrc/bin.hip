@@ -173,11 +173,17 @@ bin_kernel(const float* __restrict__ means, const float* __restrict__ scales, co
     // the cache; the others go to the overflow list
     const int S = o.tile;
     // overflow slots in record order: partition prefix, then wave and lane
+    // the lane's tile caches, all loads in flight together (the cache of a
+    // record without tiles is never written, so it is not read)
+    uint4 cch[kItems];
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) cch[j] = c[j] > 0u ? tile_cache[base + j] : make_uint4(0u, 0u, 0u, 0u);
     uint32_t nover = 0;
     bool ov[kItems];
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
-        ov[j] = bin_overflows(c[j], tile_cache, base + j);
+        // as bin_overflows, on the loaded cache
+        ov[j] = c[j] > 3u && (c[j] > (uint32_t)FS_INLINE_TILES || cch[j].y == FS_TILE_CACHE_NONE);
         nover += ov[j] ? 1u : 0u;
     }
     uint32_t over_incl = nover;
@@ -190,7 +196,7 @@ bin_kernel(const float* __restrict__ means, const float* __restrict__ scales, co
     __syncthreads();
     uint32_t over_slot = over_prefix + over_incl - nover;
     for (int w = 0; w < wave; ++w) over_slot += s_over[w];
-#pragma unroll 1
+#pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int64_t r = base + j;
         const uint64_t o0 = off;
@@ -203,7 +209,7 @@ bin_kernel(const float* __restrict__ means, const float* __restrict__ scales, co
         const int v = (int)(r / n);
         const fs_camera& cam = cams[v];
         const uint32_t tiles_x = ((uint32_t)cam.width + (uint32_t)S - 1u) / (uint32_t)S;
-        const uint4 cache = tile_cache[r];
+        const uint4 cache = cch[j];
         const uint64_t zk = cache.x;
         auto emit = [&](int k, uint32_t tx, uint32_t ty) {
             if ((uint32_t)k < c[j] && o0 + k < (uint64_t)capacity) {
