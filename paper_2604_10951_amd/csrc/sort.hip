@@ -31,6 +31,7 @@ constexpr int kMergeCap = 4096;   // entries per run sorted by chunk sorts and m
 constexpr int kLdsTiles = 16384;  // tile counts kept in LDS by the count and scatter kernels
 constexpr int kChunk = 8192;      // pairs per workgroup in the count and scatter kernels
 constexpr int kChunkThreads = 1024;
+constexpr int kPerThread = kChunk / kChunkThreads;   // pairs per thread and chunk
 constexpr int kLongGrid = 512;    // workgroups working through the long-run list
 constexpr int kLongThreads = 1024;
 constexpr int kScanItems = 4;
@@ -117,10 +118,18 @@ sort_count_kernel(const uint64_t* __restrict__ keys, const int64_t* __restrict__
         }
         return;
     }
+    // the thread's keys of the chunk, all loads in flight together
+    uint64_t kk[kPerThread];
+#pragma unroll
+    for (int u = 0; u < kPerThread; ++u) {
+        const int64_t i = c0 + threadIdx.x + (int64_t)u * kChunkThreads;
+        kk[u] = i < c1 ? keys[i] : ~0ull;
+    }
     for (uint32_t i = threadIdx.x; i < W; i += kChunkThreads) h[i] = 0;
     __syncthreads();
-    for (int64_t i = c0 + threadIdx.x; i < c1; i += kChunkThreads) {
-        const uint64_t t = keys[i] >> 32;
+#pragma unroll
+    for (int u = 0; u < kPerThread; ++u) {
+        const uint64_t t = kk[u] >> 32;
         if (t < (uint64_t)tiles) atomicAdd(&h[(uint32_t)t - lo], 1u);
     }
     __syncthreads();
@@ -247,10 +256,21 @@ sort_scatter_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restric
         }
         return;
     }
+    // the thread's pairs of the chunk, all loads in flight together; kept in
+    // registers for the scatter below
+    uint64_t kk[kPerThread];
+    uint32_t vv[kPerThread];
+#pragma unroll
+    for (int u = 0; u < kPerThread; ++u) {
+        const int64_t i = c0 + threadIdx.x + (int64_t)u * kChunkThreads;
+        kk[u] = i < c1 ? keys[i] : ~0ull;
+        vv[u] = i < c1 ? vals[i] : 0u;
+    }
     for (uint32_t i = threadIdx.x; i < W; i += kChunkThreads) h[i] = 0;
     __syncthreads();
-    for (int64_t i = c0 + threadIdx.x; i < c1; i += kChunkThreads) {
-        const uint64_t t = keys[i] >> 32;
+#pragma unroll
+    for (int u = 0; u < kPerThread; ++u) {
+        const uint64_t t = kk[u] >> 32;
         if (t < (uint64_t)tiles) atomicAdd(&h[(uint32_t)t - lo], 1u);
     }
     __syncthreads();
@@ -275,12 +295,12 @@ sort_scatter_kernel(const uint64_t* __restrict__ keys, const uint32_t* __restric
     for (int k = 0; k < kRounds; ++k)
         if (cnt[k] != 0u) h[threadIdx.x + k * kChunkThreads] = first[k] + got[k];
     __syncthreads();
-    for (int64_t i = c0 + threadIdx.x; i < c1; i += kChunkThreads) {
-        const uint64_t k = keys[i];
-        const uint64_t t = k >> 32;
+#pragma unroll
+    for (int u = 0; u < kPerThread; ++u) {
+        const uint64_t t = kk[u] >> 32;
         if (t < (uint64_t)tiles) {
             const uint32_t pos = atomicAdd(&h[(uint32_t)t - lo], 1u);
-            if ((int64_t)pos < P) out[pos] = make_uint2((uint32_t)k, vals[i]);
+            if ((int64_t)pos < P) out[pos] = make_uint2((uint32_t)kk[u], vv[u]);
         }
     }
 }
