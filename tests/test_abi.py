@@ -68,6 +68,16 @@ def test_host_only_entry_points_without_gpu():
     o8 = _lib.make_opts(topk=8, schedule=_lib.FS_SCHED_SPLIT, topk_mode=_lib.FS_TOPK_WEIGHT)
     assert lib.fs_preprocess(None, None, None, None, 0, ctypes.c_void_p(1), 1, ctypes.byref(o8), None, None,
                              None, None) == _lib.FS_OK
+    # tile modes 0-2 and the low-pass flag 0/1 only
+    o9 = _lib.make_opts(topk=8, schedule=_lib.FS_SCHED_SPLIT, tile_mode=3)
+    assert lib.fs_preprocess(None, None, None, None, 0, ctypes.c_void_p(1), 1, ctypes.byref(o9), None, None,
+                             None, None) == _lib.FS_ERR_ARG
+    o10 = _lib.make_opts(topk=8, schedule=_lib.FS_SCHED_SPLIT, tile_mode=_lib.FS_TILES_LINEARISED, lowpass=1)
+    assert lib.fs_preprocess(None, None, None, None, 0, ctypes.c_void_p(1), 1, ctypes.byref(o10), None, None,
+                             None, None) == _lib.FS_OK
+    o11 = _lib.make_opts(topk=8, schedule=_lib.FS_SCHED_SPLIT, lowpass=2)
+    assert lib.fs_preprocess(None, None, None, None, 0, ctypes.c_void_p(1), 1, ctypes.byref(o11), None, None,
+                             None, None) == _lib.FS_ERR_ARG
     # the tile cache must be 16-byte aligned
     assert lib.fs_preprocess(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 1,
                              ctypes.c_void_p(16), 1, ctypes.byref(o5), ctypes.c_void_p(16), ctypes.c_void_p(16),
