@@ -82,9 +82,9 @@ bool fs_workspace_layout(void* base, int64_t n, int32_t num_views, int64_t total
     // render stage: work queue of render blocks (at most 16 per tile: 8x8 blocks of a 32x32 tile)
     off = 0;
     w.render_ticket = static_cast<uint32_t*>(take(sizeof(uint32_t) * kRenderQueues * kTicketStride));
-    w.render_hist = static_cast<uint32_t*>(take(sizeof(uint32_t) * 64));
-    w.render_offs = static_cast<uint32_t*>(take(sizeof(uint32_t) * 64));
     w.render_max_blocks = (total_tiles > 0 ? total_tiles : 1) * 16;
+    w.render_gcnt_words = (w.render_max_blocks + 255) / 256 * 64;
+    w.render_gcnt = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)w.render_gcnt_words));
     w.render_order = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)w.render_max_blocks));
     w.sel_long = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)w.render_max_blocks));
     w.sel_counts = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)((w.render_max_blocks + 255) / 256)));

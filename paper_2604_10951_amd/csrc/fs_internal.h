@@ -899,8 +899,8 @@ struct FsWorkspace {
     uint32_t* long_list;     // tiles whose runs are longer than one wave sorts
     // render
     uint32_t* render_ticket;   // kRenderQueues tickets, kTicketStride words apart
-    uint32_t* render_hist;
-    uint32_t* render_offs;
+    uint32_t* render_gcnt;        // work order: blocks per cost bucket, per group of 256 blocks
+    int64_t render_gcnt_words;
     uint32_t* render_order;
     int64_t render_max_blocks;
     uint32_t* sel_long;     // split Top-K selection: long-list blocks, per 256-block group

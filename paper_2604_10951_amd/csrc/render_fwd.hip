@@ -824,58 +824,62 @@ FS_DEV int cost_bucket(uint32_t len) {
     return 63 - (k > 63 ? 63 : k);
 }
 
-__global__ void order_hist_kernel(const uint32_t* __restrict__ ranges, int sb2, uint32_t nblocks,
-                                  uint32_t* __restrict__ hist, uint32_t* __restrict__ ticket) {
+// Pass 1: per group of 256 blocks, its blocks per cost bucket (no atomics
+// outside LDS, nothing to clear beforehand); group 0 also zeroes the work
+// queues' tickets.
+__global__ void __launch_bounds__(256)
+order_count_kernel(const uint32_t* __restrict__ ranges, int sb2, uint32_t nblocks, uint32_t* __restrict__ gcnt,
+                   uint32_t* __restrict__ ticket) {
     __shared__ uint32_t h[64];
-    if (threadIdx.x < 64) h[threadIdx.x] = 0;
+    const uint32_t tid = threadIdx.x;
+    if (tid < 64) h[tid] = 0u;
     __syncthreads();
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t b = blockIdx.x * 256u + tid;
     if (b < nblocks) {
         const uint32_t t = b / sb2;
         atomicAdd(&h[cost_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
     }
     __syncthreads();
-    if (threadIdx.x < 64 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
-    if (b < kRenderQueues) ticket[b * kTicketStride] = 0u;
+    if (tid < 64) gcnt[blockIdx.x * 64u + tid] = h[tid];
+    if (blockIdx.x == 0 && tid < kRenderQueues) ticket[tid * kTicketStride] = 0u;
 }
 
-__global__ void order_scan_kernel(uint32_t* __restrict__ hist, uint32_t* __restrict__ offs) {
-    if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        for (int k = 0; k < 64; ++k) {
-            offs[k] = acc;
-            acc += hist[k];
-            hist[k] = 0u;   // ready for the next frame
-        }
+// Pass 2: every group finds where its blocks of each bucket start -- the
+// blocks of all groups in earlier buckets, then those of earlier groups in
+// the same bucket -- and places them (ranks within the group by LDS
+// cursors, so the order inside a bucket is not fixed).
+__global__ void __launch_bounds__(256)
+order_place_kernel(const uint32_t* __restrict__ ranges, int sb2, uint32_t nblocks, const uint32_t* __restrict__ gcnt,
+                   uint32_t ngroups, uint32_t* __restrict__ order) {
+    __shared__ uint32_t s_tot[4][64], s_bef[4][64], base[64];
+    const uint32_t tid = threadIdx.x, k = tid & 63u, qtr = tid >> 6;
+    uint32_t tot = 0u, bef = 0u;
+    for (uint32_t w = qtr; w < ngroups; w += 4u) {
+        const uint32_t c = gcnt[w * 64u + k];
+        tot += c;
+        bef += w < blockIdx.x ? c : 0u;
     }
-}
-
-// Ranks are taken in LDS per workgroup; one global atomic per (workgroup,
-// bucket) reserves the workgroup's run of positions.
-__global__ void order_scatter_kernel(const uint32_t* __restrict__ ranges, int sb2, uint32_t nblocks,
-                                     uint32_t* __restrict__ offs, uint32_t* __restrict__ order) {
-    __shared__ uint32_t cnt[64], base[64];
-    if (threadIdx.x < 64) cnt[threadIdx.x] = 0;
+    s_tot[qtr][k] = tot;
+    s_bef[qtr][k] = bef;
     __syncthreads();
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    int k = 0;
-    uint32_t local = 0;
+    if (tid < 64) {
+        const uint32_t T = s_tot[0][k] + s_tot[1][k] + s_tot[2][k] + s_tot[3][k];
+        const uint32_t B = s_bef[0][k] + s_bef[1][k] + s_bef[2][k] + s_bef[3][k];
+        uint32_t incl = T;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(incl, d, 64);
+            if ((int)tid >= d) incl += y;
+        }
+        base[k] = incl - T + B;
+    }
+    __syncthreads();
+    const uint32_t b = blockIdx.x * 256u + tid;
     if (b < nblocks) {
         const uint32_t t = b / sb2;
-        k = cost_bucket(ranges[2 * t + 1] - ranges[2 * t]);
-        local = atomicAdd(&cnt[k], 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x < 64 && cnt[threadIdx.x]) base[threadIdx.x] = atomicAdd(&offs[threadIdx.x], cnt[threadIdx.x]);
-    __syncthreads();
-    if (b < nblocks) {
-        const uint32_t pos = base[k] + local;
+        const uint32_t pos = atomicAdd(&base[cost_bucket(ranges[2 * t + 1] - ranges[2 * t])], 1u);
         if (pos < nblocks) order[pos] = b;
     }
-}
-
-__global__ void zero_u32_kernel(uint32_t* p, int count) {
-    if ((int)threadIdx.x < count) p[threadIdx.x] = 0u;
 }
 
 int device_cus() {
@@ -1001,11 +1005,10 @@ hipError_t fs_launch_block_order(const uint32_t* ranges, int sb2, uint32_t nbloc
     if (nblocks == 0) return hipSuccess;
     if ((int64_t)nblocks > ws.render_max_blocks || ws.render_order == nullptr) return hipErrorInvalidValue;
     const unsigned g = (nblocks + 255) / 256;
-    hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, ws.render_hist, 64);
-    hipLaunchKernelGGL(order_hist_kernel, dim3(g), dim3(256), 0, s, ranges, sb2, nblocks, ws.render_hist,
+    if (ws.render_gcnt == nullptr || (int64_t)g * 64 > ws.render_gcnt_words) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(order_count_kernel, dim3(g), dim3(256), 0, s, ranges, sb2, nblocks, ws.render_gcnt,
                        ws.render_ticket);
-    hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, s, ws.render_hist, ws.render_offs);
-    hipLaunchKernelGGL(order_scatter_kernel, dim3(g), dim3(256), 0, s, ranges, sb2, nblocks, ws.render_offs,
+    hipLaunchKernelGGL(order_place_kernel, dim3(g), dim3(256), 0, s, ranges, sb2, nblocks, ws.render_gcnt, g,
                        ws.render_order);
     return hipGetLastError();
 }
