@@ -379,10 +379,10 @@ FS_DEV bool fs_line_interval(const FsFootprint& fp, bool rows, int l, int lo_lim
 // lines are OR-ed into a 64-bit mask over a window of at most 64 tiles, then
 // visit(tx, ty) is called for each tile of the union, in increasing order.
 // The lines of a tile line are visited from the one nearest the conic's
-// centre outwards, and the visit stops once the mask holds every tile of the
-// candidate range in the window: no further line can add a tile, so the
-// union is unchanged (a footprint within one tile column usually needs a
-// single line solve per tile line).
+// centre outwards, and the visit stops once the mask holds every tile the
+// conic's extent along the lines reaches in the window: no further line can
+// add a tile, so the union is unchanged (a footprint within one tile column
+// usually needs a single line solve per tile line).
 template <class Visit>
 FS_DEV void fs_sweep_tiles(const FsFootprint& fp, int S, Visit&& visit) {
     const bool rows = (fp.py1 - fp.py0) <= (fp.px1 - fp.px0);
@@ -401,9 +401,33 @@ FS_DEV void fs_sweep_tiles(const FsFootprint& fp, int S, Visit&& visit) {
             if (cen > (double)l0 && cen < (double)l1) lc = (int)rint(cen);
         }
     }
+    // the tiles any line can reach: the conic's extent along the lines, with
+    // a margin of 1e-3 px (far beyond its rounding), within [s0, s1]; for a
+    // nearly degenerate conic (det < 1e-6 A C, an extent sensitive to the
+    // coefficients' rounding) the whole candidate range
+    int tt0 = ts0, tt1 = ts1;
+    {
+        const FsConic& q = fp.q;
+        double e[4];
+        if (q.A * q.C - q.B * q.B > 1e-6 * (q.A * q.C) && fs_conic_extent(q, e)) {
+            const double a0 = rows ? e[0] : e[2], a1 = rows ? e[1] : e[3];
+            const int anchor = rows ? fp.q.ax : fp.q.ay;
+            if (a0 > -4.0e6 && a1 < 4.0e6) {
+                const long long lo = (long long)ceil(a0 - 1e-3) + anchor, hi = (long long)floor(a1 + 1e-3) + anchor;
+                const int clo = fs_clampi(lo, s0, s1), chi = fs_clampi(hi, s0, s1);
+                if (clo <= chi) {
+                    tt0 = clo / S;
+                    tt1 = chi / S;
+                }
+            }
+        }
+    }
     for (int wbase = ts0; wbase <= ts1; wbase += 64) {
-        const int f1 = ts1 - wbase < 63 ? ts1 - wbase : 63;
-        const uint64_t full = f1 == 63 ? ~0ull : ((1ull << (f1 + 1)) - 1ull);   // bits ts0 - wbase (= 0) .. f1
+        // bits tt0 - wbase .. tt1 - wbase of the window (empty if outside it)
+        const int f0 = tt0 - wbase > 0 ? tt0 - wbase : 0;
+        const int f1 = tt1 - wbase < 63 ? tt1 - wbase : 63;
+        const uint64_t full = f0 > f1 ? 0ull
+                                      : ((f1 == 63 ? ~0ull : ((1ull << (f1 + 1)) - 1ull)) & ~((1ull << f0) - 1ull));
         for (int tl = l0 / S; tl <= l1 / S; ++tl) {
             uint64_t mask = 0;
             const int la = tl * S > l0 ? tl * S : l0;
