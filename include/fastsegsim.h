@@ -343,8 +343,10 @@ fs_status fs_instance_labels(const float* ins_feats, int32_t dim, const float* m
  * set, the alpha clamp) are held fixed, so only the selected surfels receive
  * gradient.  grad_records is caller scratch of num_views * n *
  * FS_GRAD_RECORD_FLOATS floats (zeroed by this call).  Gradients are summed
- * with float atomics, so their last bits depend on scheduling.  C <= 128
- * (FS_ERR_UNSUPPORTED above, and for the low-pass option).  Only the feature
+ * with float atomics, so their last bits depend on scheduling.  C <= 128,
+ * or with 1 <= topk <= 16 and C a multiple of 4 (8 for
+ * bfloat16 storage) up to 256 (512) channels (FS_ERR_UNSUPPORTED otherwise,
+ * and for the low-pass option).  Only the feature
  * image is differentiated (depth and normal outputs carry no gradient).  Any
  * tile mode works: the backward walks the same lists.  The forward outputs out_T / out_last must come
  * from fs_render_forward on the same records, vals and tile_ranges.  With

@@ -1164,6 +1164,7 @@ int fso_render_grad(const double* means, const double* scales, const double* qua
     double* alphas = (double*)malloc(sizeof(double) * mmax);
     double* Ts = (double*)malloc(sizeof(double) * mmax);
     double* gc = (double*)malloc(sizeof(double) * mmax);
+    double* gca = (double*)malloc(sizeof(double) * mmax);   /* sum_ch |g_ch c_ch| */
     int* clamped = (int*)malloc(sizeof(int) * mmax);
     uint32_t* who = (uint32_t*)malloc(sizeof(uint32_t) * mmax);
     double* d2s = (double*)malloc(sizeof(double) * mmax);
@@ -1192,15 +1193,21 @@ int fso_render_grad(const double* means, const double* scales, const double* qua
             wts[nc] = alpha * Tcur;
             clamped[nc] = cl;
             d2s[nc] = c[j].d2;
-            double dotc = 0.0;
-            for (int ch = 0; ch < C; ++ch) dotc += gp[ch] * feats[(int64_t)i * C + ch];
+            double dotc = 0.0, dota = 0.0;
+            for (int ch = 0; ch < C; ++ch) {
+                dotc += gp[ch] * feats[(int64_t)i * C + ch];
+                dota += fabs(gp[ch] * feats[(int64_t)i * C + ch]);
+            }
             gc[nc] = dotc;
+            gca[nc] = dota;
             ++nc;
             Tcur = Tn;
             if (K > 0 && nc == K) break;
         }
-        /* backward: suffix sums of w_l (g . c_l) */
-        double suffix = 0.0;
+        /* backward: suffix sums of w_l (g . c_l); with want_abs the same chain
+           on absolute values (|g_ch c_ch| summed over channels, so the scale
+           covers the rounding of the channel sums too) */
+        double suffix = 0.0, suffix_a = 0.0;
         const double x = (double)(p % W) + 0.5, y = (double)(p / W) + 0.5;
         for (int j = nc - 1; j >= 0; --j) {
             const uint32_t i = who[j];
@@ -1208,13 +1215,16 @@ int fso_render_grad(const double* means, const double* scales, const double* qua
             if (want_abs)
                 for (int ch = 0; ch < C; ++ch) afeat[(int64_t)i * C + ch] += wts[j] * fabs(gp[ch]);
             const double dalpha = Ts[j] * gc[j] - suffix / (1.0 - alphas[j]);
+            const double dalpha_a = Ts[j] * gca[j] + suffix_a / (1.0 - alphas[j]);
             suffix += wts[j] * gc[j];
+            suffix_a += wts[j] * gca[j];
             if (clamped[j]) continue;
             const double G = exp(-0.5 * d2s[j]);
             gopac[i] += G * dalpha;
-            if (want_abs) aopac[i] += fabs(G * dalpha);
+            if (want_abs) aopac[i] += G * dalpha_a;
             const double dG = opacity[i] * dalpha;
             const double dd2 = -0.5 * G * dG;
+            const double dd2_a = 0.5 * G * opacity[i] * dalpha_a;
             const double* Hi = H + 9 * i;
             const double h0 = (Hi[0] * x + Hi[1] * y) + Hi[2];
             const double h1 = (Hi[3] * x + Hi[4] * y) + Hi[5];
@@ -1223,10 +1233,12 @@ int fso_render_grad(const double* means, const double* scales, const double* qua
             const double du = 2.0 * u * dd2, dv = 2.0 * v * dd2;
             const double dh[3] = {du / h2, dv / h2, -(u * du + v * dv) / h2};
             const double xv[3] = {x, y, 1.0};
+            const double dua = 2.0 * fabs(u) * dd2_a, dva = 2.0 * fabs(v) * dd2_a, ah2 = fabs(h2);
+            const double dha[3] = {dua / ah2, dva / ah2, (fabs(u) * dua + fabs(v) * dva) / ah2};
             for (int r = 0; r < 3; ++r)
                 for (int k = 0; k < 3; ++k) {
                     dH[9 * i + 3 * r + k] += dh[r] * xv[k];
-                    if (want_abs) dHa[9 * i + 3 * r + k] += fabs(dh[r] * xv[k]);
+                    if (want_abs) dHa[9 * i + 3 * r + k] += dha[r] * fabs(xv[k]);
                 }
         }
     }
@@ -1273,6 +1285,7 @@ int fso_render_grad(const double* means, const double* scales, const double* qua
     free(alphas);
     free(Ts);
     free(gc);
+    free(gca);
     free(clamped);
     free(who);
     free(d2s);

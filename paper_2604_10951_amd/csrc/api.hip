@@ -292,7 +292,11 @@ fs_status fs_render_backward(const float* means, const float* scales, const floa
         !out_last || !grad_feat || !grad_records || !grad_means || !grad_scales || !grad_quats || !grad_opacity ||
         !grad_feats)
         return FS_ERR_ARG;
-    if (C > 128) return FS_ERR_UNSUPPORTED;   // one channel chunk per block in the backward
+    // the Top-K gradient pass takes rows of up to 64 16-byte vectors (C <= 256
+    // float32, 512 bfloat16); the full-blend backward one 128-channel chunk
+    const int ve = opts->feat_dtype == FS_FEAT_BF16 ? 8 : 4;
+    const bool topk_rows = opts->topk > 0 && opts->topk <= FS_TOPK_COMPACT_K && C % ve == 0 && C / ve <= 64;
+    if (C > 128 && !topk_rows) return FS_ERR_UNSUPPORTED;
     if (opts->topk_mode == FS_TOPK_WEIGHT) return FS_ERR_UNSUPPORTED;   // no backward of the by-weight selection
     if (opts->lowpass != 0) return FS_ERR_UNSUPPORTED;                 // no backward of the low-pass response
     FsWorkspace ws;

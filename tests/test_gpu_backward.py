@@ -3,7 +3,8 @@ gradient, the autograd wrapper, and a segmentation training loop.
 
 Bar: |g_gpu - g_oracle| <= 1e-4 * (sum of |terms| of that gradient), the
 float32 rounding scale of a sum of per-pixel terms (the oracle reports the
-absolute-term sums).  The upstream gradient is zeroed on the few pixels whose
+absolute-term sums, carried through the per-channel products g_c c_c, since
+each pixel's sum over channels is itself rounded in float32).  The upstream gradient is zeroed on the few pixels whose
 threshold decisions lie within 1e-5 of a threshold (the oracle flags them),
 so both sides differentiate the same discrete blend.
 """
@@ -193,3 +194,17 @@ def test_backward_refuses_a_frame_whose_lists_were_replaced(K):
     torch.cuda.synchronize()
     for k in got:
         torch.testing.assert_close(got[k], ref[k], rtol=1e-4, atol=1e-6)
+
+
+def test_backward_256_channels_topk():
+    """C = 256 (the precision workload's channel count), Top-K K = 8: the
+    gradient pass with 64 threads per row slot, against the FP64 oracle."""
+    _case("backward C=256 K=8")
+    scene = scenes.uniform_scene(2000, seed=6, feat_channels=253)
+    cam = scenes.centred_camera(128, 128)
+    assert scene.channels == 256
+    g = _upstream(scene, cam, 8, seed=2)
+    gpu = _gpu_grads(scene, cam, g, tile=8, topk=8)
+    ref = oracle.render_grad(scene.means, scene.scales, scene.quats, scene.opacity, scene.feats, cam, g, K=8,
+                             with_abs=True)
+    _check(gpu, ref, "C=256 K=8")
