@@ -771,7 +771,9 @@ FS_DEV void render_block_wide(int64_t block, WideShared<CPL, FT, NW, BG, EXT>& s
         if (qx < cam.width && qy < cam.height) {
             float* dst = out_feat + (cam.pixel_offset + (int64_t)qy * cam.width + qx) * C + c0 + cl;
             if (CPL == 2 && cl + 1 < clen && ((C & 1) == 0)) {
-                *reinterpret_cast<float2*>(dst) = make_float2(acc[q][0], acc[q][CPL - 1]);
+                // non-temporal: the image is not read back by this kernel
+                typedef float f32x2 __attribute__((ext_vector_type(2)));
+                __builtin_nontemporal_store(f32x2{acc[q][0], acc[q][CPL - 1]}, reinterpret_cast<f32x2*>(dst));
             } else {
 #pragma unroll
                 for (int c = 0; c < CPL; ++c)
