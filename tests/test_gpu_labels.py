@@ -103,6 +103,37 @@ def test_labels_small_against_features_and_oracle(dtype, channels, K, mode):
     assert frac > 0.3   # the comparison is not vacuous (empty pixels are ambiguous by construction)
 
 
+@pytest.mark.parametrize("K,lowpass", [(24, False), (8, True)])
+def test_labels_gather_forms(K, lowpass):
+    """K above the selection's LDS lists (the general gather), and the
+    low-pass response."""
+    _case(f"labels gather form K={K} lowpass={lowpass}")
+    scene, _ = scenes.parity_small()
+    cam = scenes.centred_camera(101, 77)
+    rast, fr, lab = _both(scene, cam, tile=8, topk=K, lowpass=lowpass)
+    _check_against_features(fr, lab, f"K={K} lowpass={lowpass}")
+    ref = oracle.render_tiled(scene, cam, 8, lowpass=lowpass, K=K, kcap=K)
+    assert _check_against_oracle(rast, lab, ref, 0, None, f"K={K} lowpass={lowpass}") > 0.3
+
+
+@pytest.mark.parametrize("mode", ["first", "weight"])
+def test_label_counters_match_features(mode):
+    """The counters (entries walked, rows, blended pairs, blocks) of a label
+    render equal those of the feature render of the same lists."""
+    _case(f"label counters {mode}")
+    scene, cam = scenes.topk_scene()
+    rast = raster.Rasterizer(cam, device=_dev(), tile=8, topk=8, topk_mode=mode, schedule="split")
+    tens = raster.scene_tensors(scene, _dev())
+    rast.render(*tens)
+    c_feat = torch.zeros(4, dtype=torch.int64, device=_dev())
+    c_lab = torch.zeros(4, dtype=torch.int64, device=_dev())
+    rast.render_forward(tens[4], counters=c_feat)
+    rast.render_labels(tens[4], counters=c_lab)
+    torch.cuda.synchronize()
+    assert torch.equal(c_feat, c_lab), (c_feat.tolist(), c_lab.tolist())
+    assert int(c_lab[2]) > 0
+
+
 def test_labels_two_views_and_empty_pixels():
     _case("labels two views")
     scene, _ = scenes.parity_small()
