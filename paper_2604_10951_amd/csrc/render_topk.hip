@@ -10,10 +10,13 @@
 // outputs.  It holds no feature data, so it runs at high occupancy and hides
 // the latency of its dependent list -> record loads behind other waves.
 //
-// Gather (one workgroup per block, lanes = (pixel, 16-byte channel vector)):
-// stages the block's lists and its rows in LDS, then every thread
-// accumulates w * c over its pixel's list in list order with the same fused
-// multiply-adds as the fused renderer, so both schedules give the same bits.
+// Gather (one workgroup per block, a few lanes per pixel, each owning some
+// 16-byte channel vectors of it): stages the block's lists and its rows in
+// LDS, then every thread accumulates w * c over its pixels' lists in list
+// order with the same fused multiply-adds as the fused renderer, so both
+// schedules give the same bits.  A thread walks its pixels' lists one after
+// the other (LDS pair read, then row read), so few pixels per thread and
+// several vectors each keep those chains short.
 // This pass is a stream: the feature image written (pixel-major, C floats per
 // pixel) dominates its traffic, and the rows it reads are shared by
 // neighbouring blocks and served mostly by L2.
@@ -702,9 +705,9 @@ topk_gather_general_kernel(const uint2* __restrict__ pairs, const int32_t* __res
 // weight) lists and counts go to LDS, then its feature rows are staged in
 // windows of W rows with direct global -> LDS loads (all of a window's loads
 // in flight together), and every pixel adds the rows of its list that fall
-// in the window, front to back.  TPP threads per pixel, each owning one
-// 16-byte channel vector of kPasses pixels of the block.
-template <typename FT, int TPP, int W, int KC, bool LABEL>
+// in the window, front to back.  TPP threads per pixel, each owning NVT
+// 16-byte channel vectors (q, q + TPP, ...) of kPasses pixels of the block.
+template <typename FT, int TPP, int W, int KC, bool LABEL, int NVT>
 __global__ void __launch_bounds__(kGatherThreads)
 topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restrict__ counts,
                        const uint32_t* __restrict__ rows, const uint32_t* __restrict__ nrows,
@@ -715,7 +718,7 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
     using V = Vec<FT, VE>;
     constexpr int kPix = kGatherThreads / TPP;   // pixels per pass
     constexpr int kPasses = 64 / kPix;           // pixels per thread
-    __shared__ __align__(16) uint4 s_rows[W * TPP];   // W rows of at most TPP vectors
+    __shared__ __align__(16) uint4 s_rows[W * TPP * NVT];   // W rows of at most TPP NVT vectors
     __shared__ uint2 s_pairs[64 * KC];   // the block's compact lists (K <= KC)
     __shared__ int s_cnt[64];
     __shared__ int s_off[64];                  // first pair of each pixel's list
@@ -727,7 +730,9 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
     const fs_camera& cam = cams[bp.view];
     const int nv = C / VE;                       // vectors per row (C % VE == 0)
     const int q = tid % TPP, sub = tid / TPP;
-    const bool has_vec = q < nv;
+    bool has_vec[NVT];
+#pragma unroll
+    for (int v = 0; v < NVT; ++v) has_vec[v] = q + v * TPP < nv;
     const uint32_t nr = nrows[block];
     const uint32_t R = nr & 0xffffu, NP = nr >> 16;   // rows and listed pairs of the block
     const uint32_t* __restrict__ rowlist = rows + block * 64 * (int64_t)K;
@@ -740,13 +745,13 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
         s_cnt[tid] = (px < cam.width && py < cam.height) ? counts[cam.pixel_offset + (int64_t)py * cam.width + px] : 0;
     }
     for (int t = tid; t < (int)R; t += kGatherThreads) s_rowid[t] = rowlist[t];
-    float acc[kPasses][VE];
+    float acc[kPasses][NVT * VE];
     int cur[kPasses];
 #pragma unroll
     for (int k = 0; k < kPasses; ++k) {
         cur[k] = 0;
 #pragma unroll
-        for (int i = 0; i < VE; ++i) acc[k][i] = 0.f;
+        for (int i = 0; i < NVT * VE; ++i) acc[k][i] = 0.f;
     }
     __syncthreads();
     if (tid < 64) {
@@ -784,12 +789,15 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
             while (j < c) {
                 const uint2 pr = s_pairs[s_off[p] + j];
                 if (pr.x >= s0 + (uint32_t)nw) break;
-                if (has_vec) {
-                    const typename V::raw f = *reinterpret_cast<const typename V::raw*>(
-                        reinterpret_cast<const unsigned char*>(s_rows) + ((pr.x - s0) * nv + q) * 16);
-                    const float w = __uint_as_float(pr.y);
+                const float w = __uint_as_float(pr.y);
 #pragma unroll
-                    for (int i = 0; i < VE; ++i) acc[k][i] = fmaf(w, V::at(f, i), acc[k][i]);
+                for (int v = 0; v < NVT; ++v) {
+                    if (has_vec[v]) {
+                        const typename V::raw f = *reinterpret_cast<const typename V::raw*>(
+                            reinterpret_cast<const unsigned char*>(s_rows) + ((pr.x - s0) * nv + q + v * TPP) * 16);
+#pragma unroll
+                        for (int i = 0; i < VE; ++i) acc[k][v * VE + i] = fmaf(w, V::at(f, i), acc[k][v * VE + i]);
+                    }
                 }
                 ++j;
             }
@@ -803,27 +811,36 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
         const int px = bp.x0 + (p & 7), py = bp.y0 + (p >> 3);
         const bool on = px < cam.width && py < cam.height;
         if constexpr (LABEL) {
-            // lane q holds channels q VE .. q VE + VE - 1, so lane order is
-            // channel order: the label is the own best of the lowest lane of
-            // the pixel whose best equals the pixel's maximum
-            float best = kNoValue;
-            int best_c = kNoChannel;
-            if (has_vec)
+            // within vector v, lane q holds channels (q + v TPP) VE .. + VE - 1,
+            // so lane order is channel order: the best of vector v is the own
+            // best of the lowest lane whose best equals the maximum; the
+            // vectors then combine in channel order
+            float m = kNoValue;
+            int label = kNoChannel;
 #pragma unroll
-                for (int i = 0; i < VE; ++i) argmax_take(acc[k][i], q * VE + i, best, best_c);
-            const float m = lanes_max<TPP>(best);   // every lane of the workgroup is here
-            const int base = (tid & 63) & ~(TPP - 1);
-            const uint64_t seg = TPP == 64 ? ~0ull : ((1ull << TPP) - 1);
-            const uint64_t hit = (__ballot(best == m) >> base) & seg;   // m is some lane's best (finite sums)
-            const int label = __shfl(best_c, base + (hit ? __builtin_ctzll(hit) : 0), 64);
+            for (int v = 0; v < NVT; ++v) {
+                float best = kNoValue;
+                int best_c = kNoChannel;
+                if (has_vec[v])
+#pragma unroll
+                    for (int i = 0; i < VE; ++i) argmax_take(acc[k][v * VE + i], (q + v * TPP) * VE + i, best, best_c);
+                const float mv = lanes_max<TPP>(best);   // every lane of the workgroup is here
+                const int base = (tid & 63) & ~(TPP - 1);
+                const uint64_t seg = TPP == 64 ? ~0ull : ((1ull << TPP) - 1);
+                const uint64_t hit = (__ballot(best == mv) >> base) & seg;   // mv is some lane's best (finite sums)
+                const int lv = __shfl(best_c, base + (hit ? __builtin_ctzll(hit) : 0), 64);
+                argmax_take(mv, lv, m, label);
+            }
             if (on && q == 0) {
                 const int64_t pix = cam.pixel_offset + (int64_t)py * cam.width + px;
                 out_label[pix] = label;
                 if (out_score) out_score[pix] = m;
             }
         } else {
-            if (on && has_vec)
-                store_vec<VE>(out_feat + (cam.pixel_offset + (int64_t)py * cam.width + px) * C, q * VE, acc[k]);
+            float* dst = out_feat + (cam.pixel_offset + (int64_t)py * cam.width + px) * C;
+#pragma unroll
+            for (int v = 0; v < NVT; ++v)
+                if (on && has_vec[v]) store_vec<VE>(dst, (q + v * TPP) * VE, &acc[k][v * VE]);
         }
     }
 }
@@ -838,23 +855,35 @@ hipError_t launch_gather(const uint2* pairs, const int32_t* counts, const uint32
     while (tpp < nv && tpp < 64) tpp <<= 1;
     if (VE > 1 && nv <= 64 && K <= kStagedK) {
         if (nblocks >= (int64_t(1) << 32)) return hipErrorInvalidValue;
-#define FS_GATHER_LDS(TPP, W)                                                                                     \
+        // Threads per pixel: 8 when the feature image is written (one store
+        // instruction then fills whole 128-B lines), 4 for labels; each
+        // thread owns NVT vectors, q, q + TPP, ..., and 64 TPP / 256 pixels,
+        // whose list walks it runs one after the other.  Measured on the
+        // 1280x720 C = 128 float32 frame (render, features / labels): 32
+        // threads x 1 vector 0.204 / 0.186 ms, 16 x 2 0.192 / 0.171, 8 x 4
+        // 0.188 / 0.162, 4 x 8 0.225 / 0.157.  Row windows of about 16 KB
+        // (32 rows of 512 B measured best for C = 128 float32 against 16,
+        // 24 and 40).
+#define FS_GATHER_LDS(TPP, W, NVT)                                                                                \
     if (K <= 8)                                                                                                    \
-        hipLaunchKernelGGL((topk_gather_lds_kernel<FT, TPP, W, 8, LABEL>), dim3((unsigned)nblocks),               \
+        hipLaunchKernelGGL((topk_gather_lds_kernel<FT, TPP, W, 8, LABEL, NVT>), dim3((unsigned)nblocks),          \
                            dim3(kGatherThreads), 0, s, pairs, counts, rows, nrows, f, C, K, cams, num_views, S,   \
                            nblocks, out_feat, out_label, out_score);                                               \
     else                                                                                                           \
-        hipLaunchKernelGGL((topk_gather_lds_kernel<FT, TPP, W, kStagedK, LABEL>), dim3((unsigned)nblocks),         \
+        hipLaunchKernelGGL((topk_gather_lds_kernel<FT, TPP, W, kStagedK, LABEL, NVT>), dim3((unsigned)nblocks),    \
                            dim3(kGatherThreads), 0, s, pairs, counts, rows, nrows, f, C, K, cams, num_views, S,   \
                            nblocks, out_feat, out_label, out_score)
-        // row windows of 4-24 KB (32 rows of 512 B measured best for C = 128
-        // float32 against 16, 24 and 40)
-        switch (tpp) {
-            case 4: FS_GATHER_LDS(4, 64); break;
-            case 8: FS_GATHER_LDS(8, 64); break;
-            case 16: FS_GATHER_LDS(16, 64); break;
-            case 32: FS_GATHER_LDS(32, 32); break;
-            default: FS_GATHER_LDS(64, 24); break;
+        constexpr int T = LABEL ? 4 : 8;
+        if (nv <= 4) {
+            FS_GATHER_LDS(4, 64, 1);
+        } else if (nv <= T) {
+            FS_GATHER_LDS(T, 64, 8 / T);
+        } else if (nv <= 16) {
+            FS_GATHER_LDS(T, 64, 16 / T);
+        } else if (nv <= 32) {
+            FS_GATHER_LDS(T, 32, 32 / T);
+        } else {
+            FS_GATHER_LDS(T, 24, 64 / T);
         }
 #undef FS_GATHER_LDS
         return hipGetLastError();
