@@ -31,6 +31,7 @@
 namespace {
 
 constexpr int kSelBatch = 32;   // list entries staged per step in the selection pass
+constexpr int kEvalPairs = 2;   // (entry, pixel) pairs a selection lane evaluates per round
 constexpr uint32_t kSelLong = 48;   // blocks with longer tile lists are selected first
 constexpr int kSelGroup = 256;       // blocks per group of the long-block list
 constexpr int kGatherThreads = 256;
@@ -297,9 +298,16 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint64_t* __restr
         }
         sm.mask[lane] = 0u;
         sel_sync<WPG>();
-        for (int k0 = 0; k0 < total; k0 += 64) {
-            const int k = k0 + lane;
-            if (k < total) {
+        // kEvalPairs pairs per lane and round, as straight-line code (pairs
+        // past the end evaluate the last pair again and set no bit), so the
+        // dependent LDS reads and FP64 chains of the pairs overlap
+        for (int k0 = 0; k0 < total; k0 += 64 * kEvalPairs) {
+            int pe[kEvalPairs], pp[kEvalPairs];
+            bool hitp[kEvalPairs];
+#pragma unroll
+            for (int u = 0; u < kEvalPairs; ++u) {
+                const int k0u = k0 + u * 64 + lane;
+                const int k = k0u < total ? k0u : total - 1;
                 int e = 0;   // the entry owning pair k: last e with pre[e] <= k
 #pragma unroll
                 for (int step = BG / 2; step > 0; step >>= 1)
@@ -317,14 +325,23 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint64_t* __restr
                         p += sh;
                     }
                 }
+                pe[u] = e;
+                pp[u] = p;
+            }
+#pragma unroll
+            for (int u = 0; u < kEvalPairs; ++u) {
+                const int e = pe[u], p = pp[u];
                 const int lx = p & 7, ly = p >> 3;
                 const FsRecord& r = sm.rec[e];
                 const double ddx = (double)(bp.x0 + lx - r.ax), ddy = (double)(bp.y0 + ly - r.ay);
                 FsResp rs = fs_response(r, ddx, ddy);
                 if constexpr (EXT)
                     if (lowpass) fs_lowpass_d2(rs, ddx, ddy, sm.mu[e].x, sm.mu[e].y);
-                if (rs.d2 <= r.k2) atomicOr(&sm.mask[p], 1u << e);
+                hitp[u] = k0 + u * 64 + lane < total && rs.d2 <= r.k2;
             }
+#pragma unroll
+            for (int u = 0; u < kEvalPairs; ++u)
+                if (hitp[u]) atomicOr(&sm.mask[pp[u]], 1u << pe[u]);
         }
         sel_sync<WPG>();
         // (b) lane = pixel: front-to-back transmittance over its accepted
