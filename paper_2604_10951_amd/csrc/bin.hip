@@ -63,15 +63,13 @@ constexpr int kPart = kThreads * kItems;        // counts per partition
 
 __global__ void zero_count_kernel(int64_t* p) { *p = 0; }
 
-FS_DEV uint32_t wave_inclusive_scan(uint32_t x) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
-    return x;
-}
+// Wave-wide inclusive prefix sum and sums of the ROCm device library (lane
+// shifts and row broadcasts in registers, no LDS round trips).
+extern "C" __device__ unsigned int __ockl_wfscan_add_u32(unsigned int, bool);
+extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_add_u32(unsigned int);
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_add_u64(unsigned long long);
+
+FS_DEV uint32_t wave_inclusive_scan(uint32_t x) { return __ockl_wfscan_add_u32(x, true); }
 
 // Pass 1 of the scan: the total count of every partition of kPart counts and
 // its number of footprints whose tiles the cache does not hold.
@@ -90,11 +88,8 @@ bin_sums_kernel(const uint32_t* __restrict__ counts, const uint4* __restrict__ t
         sum += c;
         over += bin_overflows(c, tile_cache, base + j) ? 1u : 0u;
     }
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        sum += __shfl_xor(sum, d, 64);
-        over += __shfl_xor(over, d, 64);
-    }
+    sum = __ockl_wfred_add_u64(sum);
+    over = __ockl_wfred_add_u32(over);
     if (lane == 0) {
         s_wave[wave] = sum;
         s_over[wave] = over;
@@ -135,11 +130,8 @@ bin_kernel(const float* __restrict__ means, const float* __restrict__ scales, co
         pre += sums[k];
         opre += over_sums[k];
     }
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        pre += __shfl_xor(pre, d, 64);
-        opre += __shfl_xor(opre, d, 64);
-    }
+    pre = __ockl_wfred_add_u64(pre);
+    opre = __ockl_wfred_add_u32(opre);
     if (lane == 0) {
         s_pre[wave] = pre;
         s_over_pre[wave] = opre;
@@ -186,12 +178,7 @@ bin_kernel(const float* __restrict__ means, const float* __restrict__ scales, co
         ov[j] = c[j] > 3u && (c[j] > (uint32_t)FS_INLINE_TILES || cch[j].y == FS_TILE_CACHE_NONE);
         nover += ov[j] ? 1u : 0u;
     }
-    uint32_t over_incl = nover;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(over_incl, d, 64);
-        if (lane >= d) over_incl += y;
-    }
+    const uint32_t over_incl = wave_inclusive_scan(nover);
     if (lane == 63) s_over[wave] = over_incl;
     __syncthreads();
     uint32_t over_slot = over_prefix + over_incl - nover;

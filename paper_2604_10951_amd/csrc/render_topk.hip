@@ -28,6 +28,12 @@
 // bands last: render 216 vs 209 us on the 1280x720 frame).
 #include "fs_internal.h"
 
+// Wave-wide inclusive prefix sum and or-reduction of the ROCm device library
+// (lane shifts and row broadcasts in registers, no LDS round trips).
+extern "C" __device__ int __ockl_wfscan_add_i32(int, bool);
+extern "C" __device__ unsigned int __ockl_wfscan_add_u32(unsigned int, bool);
+extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_or_u32(unsigned int);
+
 namespace {
 
 constexpr int kSelBatch = 32;   // list entries staged per step in the selection pass
@@ -122,19 +128,14 @@ FS_DEV int64_t select_block_of(int64_t nblocks, const fs_camera* cams, int S, in
     uint32_t run = 0;
     for (int64_t c0 = 0; c0 < ngroups; c0 += 64) {
         const uint32_t c = c0 + lane < ngroups ? counts[c0 + lane] : 0u;
-        uint32_t incl = c;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint32_t y = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += y;
-        }
+        const uint32_t incl = __ockl_wfscan_add_u32(c, true);
         const uint64_t past = __ballot((int64_t)(run + incl) > g);
         if (past) {
             const int l = __builtin_ctzll(past);
-            const uint32_t excl = run + __shfl(incl, l, 64) - __shfl(c, l, 64);
+            const uint32_t excl = run + __builtin_amdgcn_readlane(incl, l) - __builtin_amdgcn_readlane(c, l);
             return lng[(c0 + l) * kSelGroup + (g - excl)];
         }
-        run += __shfl(incl, 63, 64);
+        run += __builtin_amdgcn_readlane(incl, 63);
     }
     return -1;   // fewer long blocks than g + 1
 }
@@ -285,13 +286,8 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint64_t* __restr
                 ecount = __popcll(epix);
             }
         }
-        int incl = ecount;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int y = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += y;
-        }
-        const int total = __shfl(incl, 63, 64);
+        const int incl = __ockl_wfscan_add_i32(ecount, true);
+        const int total = __builtin_amdgcn_readlane(incl, 63);
         if (lane < BG) {
             sm.pre[lane] = lane < nb ? incl - ecount : total;
             sm.pixels[lane] = epix;
@@ -427,9 +423,7 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint64_t* __restr
         }
         // (c) row slots: the entries any pixel of the block blends get
         //     consecutive slots of the block's row list, in list order
-        uint32_t used = bm;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) used |= __shfl_xor(used, d, 64);
+        const uint32_t used = __ockl_wfred_or_u32(bm);
         if constexpr (KC > 0) {
             for (int j = c_start; j < cnt; ++j) {
                 const uint32_t e = sm.list[lane * KC + j].x;
@@ -526,13 +520,8 @@ topk_select_kernel(const FsRecord* __restrict__ records, const uint64_t* __restr
     }
     if constexpr (KC > 0) {
         // compact lists: pixel p's pairs after those of pixels 0 .. p - 1
-        int incl = cnt;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int y = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += y;
-        }
-        const int total = __shfl(incl, 63, 64);
+        const int incl = __ockl_wfscan_add_i32(cnt, true);
+        const int total = __builtin_amdgcn_readlane(incl, 63);
         uint2* __restrict__ dst = pairs + block * 64 * (int64_t)K + (incl - cnt);
         for (int j = 0; j < cnt; ++j) dst[j] = sm.list[lane * KC + j];
         if (lane == 0) nrows[block] = nslots | ((uint32_t)total << 16);
@@ -794,12 +783,7 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
     __syncthreads();
     if (tid < 64) {
         const int c = s_cnt[tid];
-        int incl = c;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int y = __shfl_up(incl, d, 64);
-            if (tid >= d) incl += y;
-        }
+        const int incl = __ockl_wfscan_add_i32(c, true);
         s_off[tid] = incl - c;   // visible after the staging barrier below
     }
     for (uint32_t s0 = 0; s0 < R; s0 += W) {
