@@ -36,11 +36,12 @@ FS_DEV float feat_to_f32<float>(float x) { return x; }
 template <>
 FS_DEV float feat_to_f32<uint16_t>(uint16_t x) { return bf16_to_f32(x); }
 
-FS_DEV uint32_t wave_or(uint32_t x) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) x |= __shfl_xor(x, d, 64);
-    return x;
-}
+// Wave-wide inclusive prefix sum and or-reduction of the ROCm device library
+// (lane shifts and row broadcasts in registers, no LDS round trips).
+extern "C" __device__ int __ockl_wfscan_add_i32(int, bool);
+extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_or_u32(unsigned int);
+
+FS_DEV uint32_t wave_or(uint32_t x) { return __ockl_wfred_or_u32(x); }
 
 // Bytes of a vector load of feature elements (16 B when C allows it).
 template <typename FT, bool VEC>
@@ -607,13 +608,10 @@ FS_DEV void render_block_wide(int64_t block, WideShared<CPL, FT, NW, BG, EXT>& s
                     packed = (xa - bp.x0) | ((ya - bp.y0) << 3) | (rw << 6) | (inv << 10);
                 }
             }
-            int S = cnt_e;
-#pragma unroll
-            for (int d = 1; d < 32; d <<= 1) {
-                const int y = __shfl_up(S, d, 64);
-                if (lane >= d) S += y;
-            }
-            const int M = __shfl(S, 31, 64);
+            // inclusive prefix of the entries' pair counts (lanes 0-31 hold the
+            // batch's entries; the bisection below reads only those)
+            const int S = __ockl_wfscan_add_i32(cnt_e, true);
+            const int M = __builtin_amdgcn_readlane(S, 31);
             for (int base = wave * 64; base < M; base += NT) {   // uniform per wave: every lane shuffles
                 const int m = base + lane;
                 int e = 0;

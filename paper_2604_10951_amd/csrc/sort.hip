@@ -22,6 +22,13 @@
 // count, so the sequence can be captured in a graph.
 #include "fs_internal.h"
 
+// Wave-wide inclusive prefix sum and reductions of the ROCm device library
+// (lane shifts and row broadcasts in registers, no LDS round trips).
+extern "C" __device__ unsigned int __ockl_wfscan_add_u32(unsigned int, bool);
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_add_u64(unsigned long long);
+extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_min_u32(unsigned int);
+extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_max_u32(unsigned int);
+
 namespace {
 
 constexpr int kThreads = 256;
@@ -71,12 +78,8 @@ FS_DEV void chunk_window(const uint64_t* __restrict__ keys, int64_t c0, int64_t 
             b = (uint32_t)t > b ? (uint32_t)t : b;
         }
     }
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t x = __shfl_xor(a, d, 64), y = __shfl_xor(b, d, 64);
-        a = x < a ? x : a;
-        b = y > b ? y : b;
-    }
+    a = __ockl_wfred_min_u32(a);
+    b = __ockl_wfred_max_u32(b);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0) {
         s_red[2 * wave] = a;
@@ -137,15 +140,7 @@ sort_count_kernel(const uint64_t* __restrict__ keys, const int64_t* __restrict__
         if (h[i]) atomicAdd(&cnt[lo + i], h[i]);
 }
 
-FS_DEV uint32_t wave_inclusive_scan(uint32_t x) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
-    return x;
-}
+FS_DEV uint32_t wave_inclusive_scan(uint32_t x) { return __ockl_wfscan_add_u32(x, true); }
 
 // Exclusive scan of the tile counts into ranges (single pass: partitions by
 // atomic ticket, decoupled look-back with one wave reading 64 predecessors
@@ -199,9 +194,7 @@ sort_scan_kernel(const uint32_t* __restrict__ cnt, int64_t tiles, uint32_t* __re
                 const bool found = first_pre < limit;
                 const int take = found ? first_pre + 1 : limit;
                 uint64_t v = lane < take ? (st & kValMask) : 0ull;
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) v += __shfl_xor(v, d, 64);
-                prefix += v;
+                prefix += __ockl_wfred_add_u64(v);
                 if (found) break;
                 j -= take;
                 if (take == 0) __builtin_amdgcn_s_sleep(1);
