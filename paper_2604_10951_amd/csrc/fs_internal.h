@@ -862,6 +862,36 @@ FS_DEV int64_t block_row_chunk(const fs_camera* cams, int S) {
 // i ^ j with j < 2^LOGE sit in the same lane; with larger j they are the
 // same register of lane ^ (j >> LOGE), fetched by a shuffle.  The network is
 // the textbook one (stage k, distance j, ascending where i & k == 0).
+// Value of lane (lane ^ lm) for lm in {1, 2, 4, 8, 16, 32}.  Distances
+// within a 16-lane row use data-parallel-primitive moves, which permute in
+// the vector pipeline: quad permutations for 1 and 2, the mirror of an
+// 8-lane half-row (lane ^ 7) followed by the reversal of a quad (lane ^ 3)
+// for 4, the mirror of a row (lane ^ 15) followed by the half-row mirror for
+// 8.  Longer distances go through the LDS crossbar: a swizzle within 32
+// lanes for 16, a permute for 32.
+FS_DEV uint32_t lane_xor32(uint32_t v, int lm) {
+    const int x = (int)v;
+    switch (lm) {
+        case 1: return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+        case 2: return (uint32_t)__builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+        case 4: {
+            const int h = __builtin_amdgcn_mov_dpp(x, 0x141, 0xF, 0xF, false);          // row_half_mirror
+            return (uint32_t)__builtin_amdgcn_mov_dpp(h, 0x1B, 0xF, 0xF, false);        // quad_perm [3,2,1,0]
+        }
+        case 8: {
+            const int m = __builtin_amdgcn_mov_dpp(x, 0x140, 0xF, 0xF, false);          // row_mirror
+            return (uint32_t)__builtin_amdgcn_mov_dpp(m, 0x141, 0xF, 0xF, false);       // row_half_mirror
+        }
+        case 16: return (uint32_t)__builtin_amdgcn_ds_swizzle(x, 0x1F | (16 << 10));   // xor 16 within 32 lanes
+        default: return (uint32_t)__shfl_xor(x, lm, 64);
+    }
+}
+
+FS_DEV uint64_t lane_xor64(uint64_t v, int lm) {
+    const uint32_t lo = lane_xor32((uint32_t)v, lm), hi = lane_xor32((uint32_t)(v >> 32), lm);
+    return (uint64_t)hi << 32 | lo;
+}
+
 template <int LOGE>
 FS_DEV void wave_network(uint64_t (&x)[1 << LOGE]) {
     constexpr int E = 1 << LOGE;
@@ -878,7 +908,7 @@ FS_DEV void wave_network(uint64_t (&x)[1 << LOGE]) {
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const int i = lane * E + e;
-                    const uint64_t y = __shfl_xor(x[e], lm, 64);
+                    const uint64_t y = lane_xor64(x[e], lm);
                     const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
                     const bool lt = y < x[e];
                     x[e] = (keep_min == lt) ? y : x[e];
