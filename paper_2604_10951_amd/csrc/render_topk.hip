@@ -611,7 +611,24 @@ FS_DEV void argmax_take(float x, int c, float& v, int& cv) {
 template <int TPP>
 FS_DEV void argmax_lanes(float& v, int& c) {
 #pragma unroll
-    for (int d = 1; d < TPP; d <<= 1) argmax_take(__shfl_xor(v, d, 64), __shfl_xor(c, d, 64), v, c);
+    for (int d = 1; d < TPP; d <<= 1)
+        argmax_take(__uint_as_float(lane_xor32(__float_as_uint(v), d)), (int)lane_xor32((uint32_t)c, d), v, c);
+}
+
+// Value of lane l (0 <= l < TPP) of the caller's group of TPP consecutive
+// lanes; l may differ between groups.  For groups of four, the four quad
+// broadcasts and a selection, in the vector pipeline.
+template <int TPP>
+FS_DEV int group_lane(int v, int l) {
+    if constexpr (TPP == 4) {
+        const int b0 = __builtin_amdgcn_mov_dpp(v, 0x00, 0xF, 0xF, false);   // quad_perm [0, 0, 0, 0]
+        const int b1 = __builtin_amdgcn_mov_dpp(v, 0x55, 0xF, 0xF, false);   // quad_perm [1, 1, 1, 1]
+        const int b2 = __builtin_amdgcn_mov_dpp(v, 0xAA, 0xF, 0xF, false);   // quad_perm [2, 2, 2, 2]
+        const int b3 = __builtin_amdgcn_mov_dpp(v, 0xFF, 0xF, 0xF, false);   // quad_perm [3, 3, 3, 3]
+        return l == 0 ? b0 : l == 1 ? b1 : l == 2 ? b2 : b3;
+    } else {
+        return __shfl(v, ((int)threadIdx.x & 63 & ~(TPP - 1)) + l, 64);
+    }
 }
 // Largest v over aligned groups of TPP lanes, every lane of the group
 // getting it: in-row DPP moves (quad swaps, then the mirrors within 8 and 16
@@ -663,12 +680,7 @@ topk_gather_general_kernel(const uint2* __restrict__ pairs, const int32_t* __res
             const int qx = bp.x0 + (t & 7), qy = bp.y0 + (t >> 3);
             const int c = (qx < cam.width && qy < cam.height) ? counts[cam.pixel_offset + (int64_t)qy * cam.width + qx]
                                                               : 0;
-            int incl = c;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const int y = __shfl_up(incl, d, 64);
-                if (t >= d) incl += y;
-            }
+            const int incl = __ockl_wfscan_add_i32(c, true);
             s_off[t] = incl - c;
         }
         __syncthreads();
@@ -850,7 +862,7 @@ topk_gather_lds_kernel(const uint2* __restrict__ pairs, const int32_t* __restric
                 const int base = (tid & 63) & ~(TPP - 1);
                 const uint64_t seg = TPP == 64 ? ~0ull : ((1ull << TPP) - 1);
                 const uint64_t hit = (__ballot(best == mv) >> base) & seg;   // mv is some lane's best (finite sums)
-                const int lv = __shfl(best_c, base + (hit ? __builtin_ctzll(hit) : 0), 64);
+                const int lv = group_lane<TPP>(best_c, hit ? __builtin_ctzll(hit) : 0);
                 argmax_take(mv, lv, m, label);
             }
             if (on && q == 0) {
