@@ -36,9 +36,16 @@ FS_DEV float to_f32<float>(float x) { return x; }
 template <>
 FS_DEV float to_f32<uint16_t>(uint16_t x) { return bf16_to_f32b(x); }
 
+// Wave-wide inclusive prefix sum and reductions of the ROCm device library
+// (lane shifts and row broadcasts in registers, no LDS round trips).
+extern "C" __device__ int __ockl_wfscan_add_i32(int, bool);
+extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_or_u32(unsigned int);
+extern "C" __device__ __attribute__((const)) int __ockl_wfred_max_i32(int);
+
+// Butterfly sum over the wave (every lane gets the same bits).
 FS_DEV float wave_sum(float x) {
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) x += __shfl_xor(x, d, 64);
+    for (int d = 1; d < 64; d <<= 1) x += __uint_as_float(lane_xor32(__float_as_uint(x), d));
     return x;
 }
 
@@ -110,8 +117,7 @@ render_bwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
     const int last = inside ? out_last[pix] : -1;
     // walk back from the block's last blended entry
     int maxlast = last;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) maxlast = max(maxlast, __shfl_xor(maxlast, d, 64));
+    maxlast = __ockl_wfred_max_i32(maxlast);
     if (maxlast < (int)start) return;   // nothing was blended in this block
     // a last position from another frame's lists must not walk past this
     // tile's run into the next tile's entries
@@ -172,12 +178,7 @@ render_bwd_kernel(const FsRecord* __restrict__ records, const uint32_t* __restri
                 mask |= 1u << e;
             }
         }
-        const uint32_t used = [&] {
-            uint32_t x = mask;
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) x |= __shfl_xor(x, d, 64);
-            return x;
-        }();
+        const uint32_t used = __ockl_wfred_or_u32(mask);
         const uint64_t active_px = __ballot(mask != 0u);
         // 3. feature rows of used entries
         for (int t = lane; t < BG * kChunk; t += 64) {
@@ -445,12 +446,7 @@ topk_grad_kernel(const FsRecord* __restrict__ records, const uint2* __restrict__
         // list area (the selection writes them back to back)
         const int px = bp.x0 + (tid & 7), py = bp.y0 + (tid >> 3);
         const int c = (px < cam.width && py < cam.height) ? counts[cam.pixel_offset + (int64_t)py * cam.width + px] : 0;
-        int incl = c;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int y = __shfl_up(incl, d, 64);
-            if (tid >= d) incl += y;
-        }
+        const int incl = __ockl_wfscan_add_i32(c, true);
         s_cnt[tid] = c;
         s_off[tid] = incl - c;
     }
@@ -475,12 +471,7 @@ topk_grad_kernel(const FsRecord* __restrict__ records, const uint2* __restrict__
             c[i] = b0 + i < (int)R ? s_sfill[b0 + i] : 0;
             sum += c[i];
         }
-        int incl = sum;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int y = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += y;
-        }
+        const int incl = __ockl_wfscan_add_i32(sum, true);
         if (lane == 63) s_wave[wave] = incl;
         __syncthreads();
         int off = incl - sum;
@@ -545,7 +536,7 @@ topk_grad_kernel(const FsRecord* __restrict__ records, const uint2* __restrict__
                 acc[e] = fmaf(w, gv[e], acc[e]);
             }
 #pragma unroll
-            for (int d = 1; d < TPP; d <<= 1) part += __shfl_xor(part, d, 64);
+            for (int d = 1; d < TPP; d <<= 1) part += __uint_as_float(lane_xor32(__float_as_uint(part), d));
             if (q == 0) s_D[t] = part;
         }
         if (live && has_vec) {
