@@ -908,7 +908,9 @@ FS_DEV void wave_network(uint64_t (&x)[1 << LOGE]) {
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const int i = lane * E + e;
-                    const uint64_t y = lane_xor64(x[e], lm);
+                    // with 16 keys per lane the vector pipeline is busy with the
+                    // compare-exchanges, and the LDS crossbar moves them faster
+                    const uint64_t y = LOGE <= 3 ? lane_xor64(x[e], lm) : __shfl_xor(x[e], lm, 64);
                     const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
                     const bool lt = y < x[e];
                     x[e] = (keep_min == lt) ? y : x[e];
