@@ -63,12 +63,6 @@ constexpr int kPart = kThreads * kItems;        // counts per partition
 
 __global__ void zero_count_kernel(int64_t* p) { *p = 0; }
 
-// Wave-wide inclusive prefix sum and sums of the ROCm device library (lane
-// shifts and row broadcasts in registers, no LDS round trips).
-extern "C" __device__ unsigned int __ockl_wfscan_add_u32(unsigned int, bool);
-extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_add_u32(unsigned int);
-extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_add_u64(unsigned long long);
-
 FS_DEV uint32_t wave_inclusive_scan(uint32_t x) { return __ockl_wfscan_add_u32(x, true); }
 
 // Pass 1 of the scan: the total count of every partition of kPart counts and

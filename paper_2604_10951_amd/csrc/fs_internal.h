@@ -862,6 +862,18 @@ FS_DEV int64_t block_row_chunk(const fs_camera* cams, int S) {
 // i ^ j with j < 2^LOGE sit in the same lane; with larger j they are the
 // same register of lane ^ (j >> LOGE), fetched by a shuffle.  The network is
 // the textbook one (stage k, distance j, ascending where i & k == 0).
+// Wave-wide inclusive prefix sums and reductions of the ROCm device library:
+// lane shifts and row broadcasts in registers, with no LDS round trip (a
+// chain of six shuffles costs six).  Every lane of the wave must be active.
+extern "C" __device__ int __ockl_wfscan_add_i32(int, bool);
+extern "C" __device__ unsigned int __ockl_wfscan_add_u32(unsigned int, bool);
+extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_add_u32(unsigned int);
+extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_add_u64(unsigned long long);
+extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_or_u32(unsigned int);
+extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_min_u32(unsigned int);
+extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_max_u32(unsigned int);
+extern "C" __device__ __attribute__((const)) int __ockl_wfred_max_i32(int);
+
 // Value of lane (lane ^ lm) for lm in {1, 2, 4, 8, 16, 32}.  Distances
 // within a 16-lane row use data-parallel-primitive moves, which permute in
 // the vector pipeline: quad permutations for 1 and 2, the mirror of an

@@ -36,12 +36,6 @@ FS_DEV float to_f32<float>(float x) { return x; }
 template <>
 FS_DEV float to_f32<uint16_t>(uint16_t x) { return bf16_to_f32b(x); }
 
-// Wave-wide inclusive prefix sum and reductions of the ROCm device library
-// (lane shifts and row broadcasts in registers, no LDS round trips).
-extern "C" __device__ int __ockl_wfscan_add_i32(int, bool);
-extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_or_u32(unsigned int);
-extern "C" __device__ __attribute__((const)) int __ockl_wfred_max_i32(int);
-
 // Butterfly sum over the wave (every lane gets the same bits).
 FS_DEV float wave_sum(float x) {
 #pragma unroll

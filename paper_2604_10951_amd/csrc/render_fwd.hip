@@ -36,11 +36,6 @@ FS_DEV float feat_to_f32<float>(float x) { return x; }
 template <>
 FS_DEV float feat_to_f32<uint16_t>(uint16_t x) { return bf16_to_f32(x); }
 
-// Wave-wide inclusive prefix sum and or-reduction of the ROCm device library
-// (lane shifts and row broadcasts in registers, no LDS round trips).
-extern "C" __device__ int __ockl_wfscan_add_i32(int, bool);
-extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_or_u32(unsigned int);
-
 FS_DEV uint32_t wave_or(uint32_t x) { return __ockl_wfred_or_u32(x); }
 
 // Bytes of a vector load of feature elements (16 B when C allows it).
@@ -891,7 +886,6 @@ int device_cus() {
     }
     return cus;
 }
-
 
 template <int CPL, typename FT, int WAVES, int BG, bool EXT>
 hipError_t launch(const FsRecord* records, const uint64_t* keys, const uint32_t* vals, const uint32_t* ranges,

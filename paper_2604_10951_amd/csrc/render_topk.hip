@@ -28,12 +28,6 @@
 // bands last: render 216 vs 209 us on the 1280x720 frame).
 #include "fs_internal.h"
 
-// Wave-wide inclusive prefix sum and or-reduction of the ROCm device library
-// (lane shifts and row broadcasts in registers, no LDS round trips).
-extern "C" __device__ int __ockl_wfscan_add_i32(int, bool);
-extern "C" __device__ unsigned int __ockl_wfscan_add_u32(unsigned int, bool);
-extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_or_u32(unsigned int);
-
 namespace {
 
 constexpr int kSelBatch = 32;   // list entries staged per step in the selection pass
@@ -45,7 +39,6 @@ constexpr int kGatherUnroll = 8;  // (surfel, weight) pairs whose row loads are 
 constexpr int kStagedK = 16;      // largest K of the staged gather (its lists live in LDS)
 constexpr int kCompactK = FS_TOPK_COMPACT_K;   // K up to which the selection writes compact lists
 static_assert(kStagedK <= kCompactK, "the staged gather reads compact lists");
-
 
 // KC > 0: every pixel's list (at most KC pairs) is kept in LDS during the
 // walk and written compactly at the end; KC = 0: lists written in place.

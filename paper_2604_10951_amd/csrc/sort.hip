@@ -22,13 +22,6 @@
 // count, so the sequence can be captured in a graph.
 #include "fs_internal.h"
 
-// Wave-wide inclusive prefix sum and reductions of the ROCm device library
-// (lane shifts and row broadcasts in registers, no LDS round trips).
-extern "C" __device__ unsigned int __ockl_wfscan_add_u32(unsigned int, bool);
-extern "C" __device__ __attribute__((const)) unsigned long long __ockl_wfred_add_u64(unsigned long long);
-extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_min_u32(unsigned int);
-extern "C" __device__ __attribute__((const)) unsigned int __ockl_wfred_max_u32(unsigned int);
-
 namespace {
 
 constexpr int kThreads = 256;
