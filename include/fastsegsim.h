@@ -225,7 +225,7 @@ fs_status fs_bin(const float* means, const float* scales, const float* quats, co
  *     must be ordered by the caller.
  */
 #define FS_NOALLOC_MAX_RECORDS 4194304
-#define FS_NOALLOC_SCRATCH_BYTES (FS_NOALLOC_MAX_RECORDS * 8 + 65536)
+#define FS_NOALLOC_SCRATCH_BYTES (FS_NOALLOC_MAX_RECORDS * 8 + 131072)
 fs_status fs_bin_noalloc(const float* means, const float* scales, const float* quats, const float* opacity, int64_t n,
                          const fs_camera* cams_dev, int32_t num_views, const fs_opts* opts,
                          const uint32_t* tiles_touched, const uint32_t* tile_cache, uint64_t* keys, uint32_t* vals,

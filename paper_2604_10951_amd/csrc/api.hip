@@ -5,6 +5,7 @@
 #include "fs_internal.h"
 
 int64_t fs_sort_scan_parts(int64_t total_tiles);
+int64_t fs_bin_scan_parts(int64_t items);
 
 namespace {
 
@@ -63,7 +64,7 @@ bool fs_workspace_layout(void* base, int64_t n, int32_t num_views, int64_t total
     };
     // bin stage
     const int64_t items = n * (int64_t)num_views;
-    w.scan_parts = (items + 1023) / 1024;
+    w.scan_parts = fs_bin_scan_parts(items);
     w.scan_status = static_cast<uint64_t*>(take(sizeof(uint64_t) * (size_t)(w.scan_parts > 0 ? w.scan_parts : 1)));
     w.scan_ticket = static_cast<uint32_t*>(take(sizeof(uint32_t) * 16));
     w.bin_over_sums = static_cast<uint32_t*>(take(sizeof(uint32_t) * (size_t)(w.scan_parts > 0 ? w.scan_parts : 1)));

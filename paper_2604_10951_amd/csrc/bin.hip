@@ -3,8 +3,9 @@
 // intersection assigns a surfel to gets one list entry).
 //
 // Two passes over the counts: the first writes the total of every partition
-// of 1024 counts; the second has every partition add up the totals before it
-// (no workgroup ever waits on another), scan its own counts with wave-level
+// of 512 counts; the second has every partition add up the totals before it
+// (no workgroup ever waits on another; with many partitions one workgroup
+// scans the totals in between instead), scan its own counts with wave-level
 // prefix sums and emit its keys.  Emission takes the depth key and the tiles
 // fs_preprocess kept (up to FS_INLINE_TILES of them, as ids or as offsets
 // from a base tile); the other footprints are queued and re-derived by a
@@ -58,8 +59,10 @@ FS_DEV bool bin_overflows(uint32_t c, const uint4* __restrict__ tile_cache, int6
 }
 
 constexpr int kThreads = 256;
-constexpr int kItems = 4;                       // counts per lane
+constexpr int kItems = 2;                       // counts per lane (4: bin 21.6 us, 2: 19.5 us on the
+                                                // 1M-surfel 1280x720 frame; 8: 27.5 us)
 constexpr int kPart = kThreads * kItems;        // counts per partition
+constexpr int64_t kSumParts = 4096;             // partitions up to which each sums those before it
 
 __global__ void zero_count_kernel(int64_t* p) { *p = 0; }
 
@@ -101,8 +104,56 @@ bin_sums_kernel(const uint32_t* __restrict__ counts, const uint4* __restrict__ t
     }
 }
 
-// Pass 2: every partition adds up the totals before it (in parallel, no
-// inter-workgroup waiting), scans its counts and emits its pairs.
+// Pass 1b: the partitions' exclusive prefixes of the totals and overflow
+// counts, in place, by one workgroup walking them in rounds of 1024.
+__global__ void __launch_bounds__(1024)
+bin_prefix_kernel(uint64_t* __restrict__ sums, uint32_t* __restrict__ over_sums, int64_t parts) {
+    __shared__ uint64_t s_w[16];
+    __shared__ uint32_t s_o[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint64_t carry = 0;
+    uint32_t ocarry = 0;
+    for (int64_t b0 = 0; b0 < parts; b0 += 1024) {
+        const int64_t k = b0 + tid;
+        const uint64_t v = k < parts ? sums[k] : 0ull;
+        const uint32_t ov = k < parts ? over_sums[k] : 0u;
+        uint64_t vi = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t y = __shfl_up(vi, d, 64);
+            if (lane >= d) vi += y;
+        }
+        const uint32_t oi = __ockl_wfscan_add_u32(ov, true);
+        if (lane == 63) {
+            s_w[wave] = vi;
+            s_o[wave] = oi;
+        }
+        __syncthreads();
+        uint64_t wex = 0, tot = 0;
+        uint32_t owex = 0, otot = 0;
+        for (int w = 0; w < 16; ++w) {
+            const uint64_t x = s_w[w];
+            const uint32_t y = s_o[w];
+            if (w < wave) {
+                wex += x;
+                owex += y;
+            }
+            tot += x;
+            otot += y;
+        }
+        if (k < parts) {
+            sums[k] = carry + wex + (vi - v);
+            over_sums[k] = ocarry + owex + (oi - ov);
+        }
+        carry += tot;
+        ocarry += otot;
+        __syncthreads();   // s_w and s_o are rewritten in the next round
+    }
+}
+
+// Pass 2: every partition takes the total of the partitions before it
+// (summed here when they are few, read from the prefix pass otherwise), scans
+// its counts and emits its pairs.
 __global__ void __launch_bounds__(kThreads)
 bin_kernel(const float* __restrict__ means, const float* __restrict__ scales, const float* __restrict__ quats,
            const float* __restrict__ opacity, int64_t n, const fs_camera* __restrict__ cams, fs_opts o,
@@ -110,19 +161,21 @@ bin_kernel(const float* __restrict__ means, const float* __restrict__ scales, co
            uint2* __restrict__ overflow, uint64_t* __restrict__ keys,
            uint32_t* __restrict__ vals, int64_t capacity, int64_t* __restrict__ num_pairs,
            const uint64_t* __restrict__ sums, const uint32_t* __restrict__ over_sums,
-           uint32_t* __restrict__ over_total, int64_t parts) {
+           uint32_t* __restrict__ over_total, int64_t parts, int prefixed) {
     __shared__ uint64_t s_wave[kThreads / 64];
     __shared__ uint64_t s_pre[kThreads / 64];
     __shared__ uint32_t s_over[kThreads / 64];
     __shared__ uint32_t s_over_pre[kThreads / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t part = blockIdx.x;
-    // prefixes: totals of partitions [0, part)
+    // totals of partitions [0, part)
     uint64_t pre = 0;
     uint32_t opre = 0;
-    for (int64_t k = tid; k < part; k += kThreads) {
-        pre += sums[k];
-        opre += over_sums[k];
+    if (!prefixed) {
+        for (int64_t k = tid; k < part; k += kThreads) {
+            pre += sums[k];
+            opre += over_sums[k];
+        }
     }
     pre = __ockl_wfred_add_u64(pre);
     opre = __ockl_wfred_add_u32(opre);
@@ -150,9 +203,9 @@ bin_kernel(const float* __restrict__ means, const float* __restrict__ scales, co
         prefix += s_pre[w];
         over_prefix += s_over_pre[w];
     }
-    if (tid == 0 && part == parts - 1) {
-        *num_pairs = (int64_t)(prefix + total);
-        *over_total = over_prefix + over_sums[part];
+    if (prefixed) {
+        prefix = sums[part];
+        over_prefix = over_sums[part];
     }
     uint64_t off = prefix + wave_excl + (incl - sum);
     // emission: footprints whose tiles fs_preprocess kept are emitted from
@@ -177,6 +230,12 @@ bin_kernel(const float* __restrict__ means, const float* __restrict__ scales, co
     __syncthreads();
     uint32_t over_slot = over_prefix + over_incl - nover;
     for (int w = 0; w < wave; ++w) over_slot += s_over[w];
+    if (tid == 0 && part == parts - 1) {
+        uint32_t own = 0;
+        for (int w = 0; w < kThreads / 64; ++w) own += s_over[w];
+        *num_pairs = (int64_t)(prefix + total);
+        *over_total = over_prefix + own;
+    }
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
         const int64_t r = base + j;
@@ -277,21 +336,33 @@ bin_overflow_kernel(const float* __restrict__ means, const float* __restrict__ s
 
 }  // namespace
 
+// Partitions of the bin stage's scan over `items` tile counts (its
+// workspace holds one 64-bit total and one overflow count per partition).
+int64_t fs_bin_scan_parts(int64_t items) { return (items + kPart - 1) / kPart; }
+
 hipError_t fs_launch_bin(const float* means, const float* scales, const float* quats, const float* opacity, int64_t n,
                          const fs_camera* cams, int32_t num_views, const fs_opts& o, const uint32_t* tiles_touched,
                          const uint32_t* tile_cache, uint64_t* keys, uint32_t* vals, int64_t capacity,
                          int64_t* num_pairs, const FsWorkspace& ws, hipStream_t s) {
     const int64_t items = n * (int64_t)num_views;
-    const int64_t parts = (items + kPart - 1) / kPart;
+    const int64_t parts = fs_bin_scan_parts(items);
     if (parts == 0) {
         hipLaunchKernelGGL(zero_count_kernel, dim3(1), dim3(1), 0, s, num_pairs);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(bin_sums_kernel, dim3((unsigned)parts), dim3(kThreads), 0, s, tiles_touched,
                        reinterpret_cast<const uint4*>(tile_cache), items, ws.scan_status, ws.bin_over_sums);
+    // each partition sums the totals before it while they are few (no extra
+    // launch); beyond that, one workgroup scans them first (the summing is
+    // quadratic in the partition count: the 1M-surfel frame's 1,954
+    // partitions bin in 19.5 us summing and 24.2 us with the scan, the
+    // 16-view frame's 31,250 take 0.24 ms summing)
+    const int prefixed = parts > kSumParts ? 1 : 0;
+    if (prefixed)
+        hipLaunchKernelGGL(bin_prefix_kernel, dim3(1), dim3(1024), 0, s, ws.scan_status, ws.bin_over_sums, parts);
     hipLaunchKernelGGL(bin_kernel, dim3((unsigned)parts), dim3(kThreads), 0, s, means, scales, quats, opacity, n, cams, o,
                        tiles_touched, reinterpret_cast<const uint4*>(tile_cache), items, ws.bin_overflow, keys, vals,
-                       capacity, num_pairs, ws.scan_status, ws.bin_over_sums, ws.scan_ticket + 1, parts);
+                       capacity, num_pairs, ws.scan_status, ws.bin_over_sums, ws.scan_ticket + 1, parts, prefixed);
     // overflow records: a grid of about one lane per 16 records, each lane striding
     const int64_t ob = (items / 16 + kThreads - 1) / kThreads;
     const unsigned oblocks = (unsigned)(ob < 1 ? 1 : (ob > 4096 ? 4096 : ob));
