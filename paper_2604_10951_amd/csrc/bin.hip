@@ -105,49 +105,73 @@ bin_sums_kernel(const uint32_t* __restrict__ counts, const uint4* __restrict__ t
 }
 
 // Pass 1b: the partitions' exclusive prefixes of the totals and overflow
-// counts, in place, by one workgroup walking them in rounds of 1024.
+// counts, in place, by one workgroup walking them in tiles of 8192: each
+// tile is loaded coalesced into LDS, every thread scans eight consecutive
+// entries there, one workgroup scan places the threads, and the tile is
+// written back coalesced.
 __global__ void __launch_bounds__(1024)
 bin_prefix_kernel(uint64_t* __restrict__ sums, uint32_t* __restrict__ over_sums, int64_t parts) {
+    constexpr int kTile = 8192, kPer = kTile / 1024;
+    __shared__ uint64_t s_v[kTile];
+    __shared__ uint32_t s_ov[kTile];
     __shared__ uint64_t s_w[16];
     __shared__ uint32_t s_o[16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint64_t carry = 0;
     uint32_t ocarry = 0;
-    for (int64_t b0 = 0; b0 < parts; b0 += 1024) {
-        const int64_t k = b0 + tid;
-        const uint64_t v = k < parts ? sums[k] : 0ull;
-        const uint32_t ov = k < parts ? over_sums[k] : 0u;
-        uint64_t vi = v;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const uint64_t y = __shfl_up(vi, d, 64);
-            if (lane >= d) vi += y;
-        }
-        const uint32_t oi = __ockl_wfscan_add_u32(ov, true);
-        if (lane == 63) {
-            s_w[wave] = vi;
-            s_o[wave] = oi;
+    for (int64_t b0 = 0; b0 < parts; b0 += kTile) {
+        const int n = parts - b0 < kTile ? (int)(parts - b0) : kTile;
+        for (int i = tid; i < kTile; i += 1024) {
+            s_v[i] = i < n ? sums[b0 + i] : 0ull;
+            s_ov[i] = i < n ? over_sums[b0 + i] : 0u;
         }
         __syncthreads();
-        uint64_t wex = 0, tot = 0;
-        uint32_t owex = 0, otot = 0;
-        for (int w = 0; w < 16; ++w) {
-            const uint64_t x = s_w[w];
-            const uint32_t y = s_o[w];
-            if (w < wave) {
-                wex += x;
-                owex += y;
-            }
-            tot += x;
-            otot += y;
+        uint64_t t = 0;
+        uint32_t ot = 0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            t += s_v[tid * kPer + j];
+            ot += s_ov[tid * kPer + j];
         }
-        if (k < parts) {
-            sums[k] = carry + wex + (vi - v);
-            over_sums[k] = ocarry + owex + (oi - ov);
+        uint64_t ti = t;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint64_t y = __shfl_up(ti, d, 64);
+            if (lane >= d) ti += y;
+        }
+        const uint32_t oti = __ockl_wfscan_add_u32(ot, true);
+        if (lane == 63) {
+            s_w[wave] = ti;
+            s_o[wave] = oti;
+        }
+        __syncthreads();
+        uint64_t run = carry + (ti - t), tot = 0;
+        uint32_t orun = ocarry + (oti - ot), otot = 0;
+        for (int w = 0; w < 16; ++w) {
+            if (w < wave) {
+                run += s_w[w];
+                orun += s_o[w];
+            }
+            tot += s_w[w];
+            otot += s_o[w];
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const uint64_t v = s_v[tid * kPer + j];
+            const uint32_t ov = s_ov[tid * kPer + j];
+            s_v[tid * kPer + j] = run;
+            s_ov[tid * kPer + j] = orun;
+            run += v;
+            orun += ov;
         }
         carry += tot;
         ocarry += otot;
-        __syncthreads();   // s_w and s_o are rewritten in the next round
+        __syncthreads();
+        for (int i = tid; i < n; i += 1024) {
+            sums[b0 + i] = s_v[i];
+            over_sums[b0 + i] = s_ov[i];
+        }
+        __syncthreads();   // the tile buffers and s_w, s_o are rewritten in the next round
     }
 }
 
